@@ -1,0 +1,961 @@
+/*
+ * mpx_oracle.c -- plain, slow, sequential CPU oracle for branch-free
+ * multicomponent (DD / TD / QD, and binary32 float-float) arithmetic.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or table with the HIP
+ * library; the two are written independently from the paper.
+ *
+ * Paper: T. Kouya, "Acceleration of multicomponent multiple-precision
+ * arithmetic with branch-free algorithms and SIMD vectorization"
+ * (arXiv 2603.14926).  Every function names the passage it follows.
+ *
+ * Arithmetic model (Section 2, opening paragraphs): IEEE binary64 (binary32
+ * for float-float) with round-to-nearest-even, every value a normalised float.
+ * Build with  -O2 -ffp-contract=off -fno-fast-math  so that no a*b+c is fused
+ * behind our back; the only fused operations are the explicit fma()/fmaf()
+ * calls of TwoProd.  All loops run in a fixed sequential order; the optional
+ * OpenMP loops parallelise only over independent outputs, so results do not
+ * depend on the thread count.
+ *
+ * Number layout used by the array entry points: a multicomponent number is the
+ * unevaluated sum of K doubles; component c of element i of a vector lives at
+ * base[c*ps + i] ("component planes"), of a row-major matrix at
+ * base[c*ps + row*ld + col].
+ *
+ * A build with -DMPXO_COUNT counts every floating-point operation by kind
+ * (add, sub, mul, fma) so the operation counts printed in Tables 1 and 2 can
+ * be checked.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <stdlib.h>
+
+/* ------------------------------------------------------------------------ */
+/* Operation counting (Tables 1 and 2 count additions, subtractions,         */
+/* multiplications and FMAs separately; negating an FMA operand is free).    */
+/* ------------------------------------------------------------------------ */
+#ifdef MPXO_COUNT
+static long long cnt_add, cnt_sub, cnt_mul, cnt_fma;
+#define OP_ADD(a, b) (cnt_add++, (a) + (b))
+#define OP_SUB(a, b) (cnt_sub++, (a) - (b))
+#define OP_MUL(a, b) (cnt_mul++, (a) * (b))
+#define OP_FMA(a, b, c) (cnt_fma++, fma((a), (b), (c)))
+#define OP_FMAF(a, b, c) (cnt_fma++, fmaf((a), (b), (c)))
+void orc_count_reset(void) { cnt_add = cnt_sub = cnt_mul = cnt_fma = 0; }
+void orc_count_get(long long out[4]) {
+    out[0] = cnt_add; out[1] = cnt_sub; out[2] = cnt_mul; out[3] = cnt_fma;
+}
+#else
+#define OP_ADD(a, b) ((a) + (b))
+#define OP_SUB(a, b) ((a) - (b))
+#define OP_MUL(a, b) ((a) * (b))
+#define OP_FMA(a, b, c) fma((a), (b), (c))
+#define OP_FMAF(a, b, c) fmaf((a), (b), (c))
+void orc_count_reset(void) {}
+void orc_count_get(long long out[4]) { out[0] = out[1] = out[2] = out[3] = -1; }
+#endif
+
+#ifdef _OPENMP
+#include <omp.h>
+void orc_set_threads(int t) { omp_set_num_threads(t); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+#else
+void orc_set_threads(int t) { (void)t; }
+int orc_get_threads(void) { return 1; }
+#endif
+
+int orc_counting_build(void) {
+#ifdef MPXO_COUNT
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Error-free transformations (Section 2: QuickTwoSum, TwoSum, TwoProd).     */
+/* ------------------------------------------------------------------------ */
+
+/* QuickTwoSum: s = fl(a+b) and its error, exact when |a| >= |b|. */
+static void quick_two_sum(double a, double b, double *s, double *e) {
+    double sum = OP_ADD(a, b);
+    double back = OP_SUB(sum, a);
+    *e = OP_SUB(b, back);
+    *s = sum;
+}
+
+/* TwoSum: s = fl(a+b) and its error, exact for any a, b. */
+static void two_sum(double a, double b, double *s, double *e) {
+    double sum = OP_ADD(a, b);
+    double v = OP_SUB(sum, a);
+    double a_err = OP_SUB(a, OP_SUB(sum, v));
+    double b_err = OP_SUB(b, v);
+    *e = OP_ADD(a_err, b_err);
+    *s = sum;
+}
+
+/* TwoProd with FMA: p = fl(a*b), e = a*b - p exactly. */
+static void two_prod(double a, double b, double *p, double *e) {
+    double prod = OP_MUL(a, b);
+    *e = OP_FMA(a, b, -prod);
+    *p = prod;
+}
+
+/* binary32 versions of the same three transformations (DS / float-float). */
+static void quick_two_sum_f(float a, float b, float *s, float *e) {
+    float sum = OP_ADD(a, b);
+    float back = OP_SUB(sum, a);
+    *e = OP_SUB(b, back);
+    *s = sum;
+}
+static void two_sum_f(float a, float b, float *s, float *e) {
+    float sum = OP_ADD(a, b);
+    float v = OP_SUB(sum, a);
+    float a_err = OP_SUB(a, OP_SUB(sum, v));
+    float b_err = OP_SUB(b, v);
+    *e = OP_ADD(a_err, b_err);
+    *s = sum;
+}
+static void two_prod_f(float a, float b, float *p, float *e) {
+    float prod = OP_MUL(a, b);
+    *e = OP_FMAF(a, b, -prod);
+    *p = prod;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Double-word (Section 2.1): DWBFAdd and DWBFMul (Zhang & Aiken), and the   */
+/* QD-default DWMul which is the same operation sequence as DWBFMul once its */
+/* final "QuickTwoProd" is read as QuickTwoSum.                              */
+/* ------------------------------------------------------------------------ */
+
+/* DWBFAdd: branch-free accurate double-word addition. */
+static void dw_bf_add(const double a[2], const double b[2], double c[2]) {
+    double g1, g1e, g2, g2e, g3, g3e, g4, g5;
+    two_sum(a[0], b[0], &g1, &g1e);
+    two_sum(a[1], b[1], &g2, &g2e);
+    quick_two_sum(g1, g2, &g3, &g3e);
+    g4 = OP_ADD(g1e, g2e);
+    g5 = OP_ADD(g4, g3e);
+    quick_two_sum(g3, g5, &c[0], &c[1]);
+}
+
+/* DWBFMul: all products first, then branch-free error handling. */
+static void dw_bf_mul(const double a[2], const double b[2], double c[2]) {
+    double p00, pe00, p01, p10, g1, g2;
+    two_prod(a[0], b[0], &p00, &pe00);
+    p01 = OP_MUL(a[0], b[1]);
+    p10 = OP_MUL(a[1], b[0]);
+    g1 = OP_ADD(p01, p10);
+    g2 = OP_ADD(pe00, g1);
+    quick_two_sum(p00, g2, &c[0], &c[1]);
+}
+
+/* The same two algorithms on binary32 components (float-float, "DS"). */
+static void ff_bf_add(const float a[2], const float b[2], float c[2]) {
+    float g1, g1e, g2, g2e, g3, g3e, g4, g5;
+    two_sum_f(a[0], b[0], &g1, &g1e);
+    two_sum_f(a[1], b[1], &g2, &g2e);
+    quick_two_sum_f(g1, g2, &g3, &g3e);
+    g4 = OP_ADD(g1e, g2e);
+    g5 = OP_ADD(g4, g3e);
+    quick_two_sum_f(g3, g5, &c[0], &c[1]);
+}
+static void ff_bf_mul(const float a[2], const float b[2], float c[2]) {
+    float p00, pe00, p01, p10, g1, g2;
+    two_prod_f(a[0], b[0], &p00, &pe00);
+    p01 = OP_MUL(a[0], b[1]);
+    p10 = OP_MUL(a[1], b[0]);
+    g1 = OP_ADD(p01, p10);
+    g2 = OP_ADD(pe00, g1);
+    quick_two_sum_f(p00, g2, &c[0], &c[1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Triple-word (Section 2.2): TWBFAdd and TWBFMul.  Variable names follow    */
+/* the paper's (letter = lane of the computation, digit = step).  Inputs are */
+/* called x[], y[] here because the paper reuses a..i as temporaries.        */
+/* ------------------------------------------------------------------------ */
+
+static void tw_bf_add(const double x[3], const double y[3], double c[3]) {
+    double a1, b1, c1, d1, e1, f1;
+    double a2, c2, b2, d2, e2;
+    double a3, d3, b3, c3, c4, c5, d5, b6, c6, b7, c7;
+    two_sum(x[0], y[0], &a1, &b1);
+    two_sum(x[1], y[1], &c1, &d1);
+    two_sum(x[2], y[2], &e1, &f1);
+    quick_two_sum(a1, c1, &a2, &c2);
+    b2 = OP_ADD(b1, f1);
+    two_sum(d1, e1, &d2, &e2);
+    quick_two_sum(a2, d2, &a3, &d3);
+    two_sum(b2, c2, &b3, &c3);
+    c4 = OP_ADD(c3, e2);
+    two_sum(c4, d3, &c5, &d5);
+    two_sum(b3, c5, &b6, &c6);
+    quick_two_sum(a3, b6, &c[0], &b7);
+    c7 = OP_ADD(c6, d5);
+    quick_two_sum(b7, c7, &c[1], &c[2]);
+}
+
+static void tw_bf_mul(const double x[3], const double y[3], double c[3]) {
+    double a0, b0, c0, e0, d0, f0, g0, h0, i0;
+    double c1, d1, e1, g1, b2, c2, g2, a3, b3, c3, e3, c4, b5, c5, b6;
+    two_prod(x[0], y[0], &a0, &b0);
+    two_prod(x[0], y[1], &c0, &e0);
+    two_prod(x[1], y[0], &d0, &f0);
+    g0 = OP_MUL(x[0], y[2]);
+    h0 = OP_MUL(x[1], y[1]);
+    i0 = OP_MUL(x[2], y[0]);
+    two_sum(c0, d0, &c1, &d1);
+    e1 = OP_ADD(e0, f0);
+    g1 = OP_ADD(g0, i0);
+    two_sum(b0, c1, &b2, &c2);
+    g2 = OP_ADD(g1, h0);
+    quick_two_sum(a0, b2, &a3, &b3);
+    c3 = OP_ADD(c2, d1);
+    e3 = OP_ADD(e1, g2);
+    c4 = OP_ADD(c3, e3);
+    quick_two_sum(b3, c4, &b5, &c5);
+    quick_two_sum(a3, b5, &c[0], &b6);
+    quick_two_sum(b6, c5, &c[1], &c[2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quad-word (Section 2.3): QWBFAdd and QDBFMul.                             */
+/* ------------------------------------------------------------------------ */
+
+static void qw_bf_add(const double x[4], const double y[4], double c[4]) {
+    double a1, b1, c1, d1, e1, f1, g1, h1;
+    double a2, c2, b2, d2, e2, f2, g2;
+    double b3, g3, c3, d3, e3, f3;
+    double a4, c4, d4, e4, b5, d5, e5, b6, c6, d6, e6;
+    double a7, b7, c7, d7, e8, b8, c8, d9, b10, c10, d10, c11;
+    two_sum(x[0], y[0], &a1, &b1);
+    two_sum(x[1], y[1], &c1, &d1);
+    two_sum(x[2], y[2], &e1, &f1);
+    two_sum(x[3], y[3], &g1, &h1);
+    quick_two_sum(a1, c1, &a2, &c2);
+    b2 = OP_ADD(b1, h1);
+    two_sum(d1, e1, &d2, &e2);
+    two_sum(f1, g1, &f2, &g2);
+    two_sum(b2, g2, &b3, &g3);
+    quick_two_sum(c2, d2, &c3, &d3);
+    two_sum(e2, f2, &e3, &f3);
+    quick_two_sum(a2, c3, &a4, &c4);
+    quick_two_sum(d3, e3, &d4, &e4);
+    two_sum(b3, d4, &b5, &d5);
+    e5 = OP_ADD(e4, f3);
+    two_sum(b5, c4, &b6, &c6);
+    two_sum(d5, e5, &d6, &e6);
+    quick_two_sum(a4, b6, &a7, &b7);
+    quick_two_sum(c6, d6, &c7, &d7);
+    e8 = OP_ADD(e6, g3);
+    quick_two_sum(b7, c7, &b8, &c8);
+    d9 = OP_ADD(d7, e8);
+    quick_two_sum(a7, b8, &c[0], &b10);
+    quick_two_sum(c8, d9, &c10, &d10);
+    quick_two_sum(b10, c10, &c[1], &c11);
+    quick_two_sum(c11, d10, &c[2], &c[3]);
+}
+
+static void qd_bf_mul(const double x[4], const double y[4], double c[4]) {
+    double a0, b0, c0, e0, d0, f0, g0, j0, h0, k0, i0, l0, m0, n0, o0, p0;
+    double c1, d1, e1, f1, g1, i1, j1, m1, n1;
+    double b2, c2, e2, h2, f2, i2, m2;
+    double a3, b3, c3, d3, e3, g3, f3, h3;
+    double c4, e4, d4, f4, d5, c6, d6, b7, c7, d7, b8, c8, d8, c9;
+    two_prod(x[0], y[0], &a0, &b0);
+    two_prod(x[0], y[1], &c0, &e0);
+    two_prod(x[1], y[0], &d0, &f0);
+    two_prod(x[0], y[2], &g0, &j0);
+    two_prod(x[1], y[1], &h0, &k0);
+    two_prod(x[2], y[0], &i0, &l0);
+    m0 = OP_MUL(x[0], y[3]);
+    n0 = OP_MUL(x[1], y[2]);
+    o0 = OP_MUL(x[2], y[1]);
+    p0 = OP_MUL(x[3], y[0]);
+    two_sum(c0, d0, &c1, &d1);
+    two_sum(e0, f0, &e1, &f1);
+    two_sum(g0, i0, &g1, &i1);
+    j1 = OP_ADD(j0, l0);
+    m1 = OP_ADD(m0, p0);
+    n1 = OP_ADD(n0, o0);
+    two_sum(b0, c1, &b2, &c2);
+    two_sum(e1, h0, &e2, &h2);
+    f2 = OP_ADD(f1, j1);
+    i2 = OP_ADD(i1, k0);
+    m2 = OP_ADD(m1, n1);
+    quick_two_sum(a0, b2, &a3, &b3);
+    quick_two_sum(c2, d1, &c3, &d3);
+    two_sum(e2, g1, &e3, &g3);
+    f3 = OP_ADD(f2, m2);
+    h3 = OP_ADD(h2, i2);
+    two_sum(c3, e3, &c4, &e4);
+    d4 = OP_ADD(d3, h3);
+    f4 = OP_ADD(f3, g3);
+    d5 = OP_ADD(d4, e4);
+    two_sum(c4, d5, &c6, &d6);
+    two_sum(b3, c6, &b7, &c7);
+    d7 = OP_ADD(d6, f4);
+    quick_two_sum(a3, b7, &c[0], &b8);
+    two_sum(c7, d7, &c8, &d8);
+    two_sum(b8, c8, &c[1], &c9);
+    quick_two_sum(c9, d8, &c[2], &c[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* K-generic dispatch: K = 2 (DD), 3 (TD), 4 (QD).                           */
+/* ------------------------------------------------------------------------ */
+
+static void mp_add(int K, const double *a, const double *b, double *c) {
+    double t[4];
+    if (K == 2) dw_bf_add(a, b, t);
+    else if (K == 3) tw_bf_add(a, b, t);
+    else qw_bf_add(a, b, t);
+    memcpy(c, t, sizeof(double) * K);
+}
+static void mp_mul(int K, const double *a, const double *b, double *c) {
+    double t[4];
+    if (K == 2) dw_bf_mul(a, b, t);
+    else if (K == 3) tw_bf_mul(a, b, t);
+    else qd_bf_mul(a, b, t);
+    memcpy(c, t, sizeof(double) * K);
+}
+static void mp_neg(int K, const double *a, double *c) {
+    for (int i = 0; i < K; i++) c[i] = -a[i];
+}
+/* Subtraction is addition of the negated operand (Section 2). */
+static void mp_sub(int K, const double *a, const double *b, double *c) {
+    double nb[4];
+    mp_neg(K, b, nb);
+    mp_add(K, a, nb, c);
+}
+static void mp_zero(int K, double *c) { for (int i = 0; i < K; i++) c[i] = 0.0; }
+static void mp_set_d(int K, double v, double *c) { mp_zero(K, c); c[0] = v; }
+static void mp_ldexp(int K, const double *a, int e, double *c) {
+    for (int i = 0; i < K; i++) c[i] = ldexp(a[i], e);
+}
+
+static void gather(int K, const double *base, int64_t ps, int64_t idx, double *v) {
+    for (int c = 0; c < K; c++) v[c] = base[c * ps + idx];
+}
+static void scatter(int K, double *base, int64_t ps, int64_t idx, const double *v) {
+    for (int c = 0; c < K; c++) base[c * ps + idx] = v[c];
+}
+
+/* Single-number entry points (used by the exact-arithmetic tests). */
+void orc_op1(int K, int op, const double *a, const double *b, double *c) {
+    if (op == 0) mp_add(K, a, b, c);
+    else mp_mul(K, a, b, c);
+}
+void orc_ff_op1(int op, const float *a, const float *b, float *c) {
+    float t[2];
+    if (op == 0) ff_bf_add(a, b, t);
+    else ff_bf_mul(a, b, t);
+    c[0] = t[0]; c[1] = t[1];
+}
+void orc_eft(int which, double a, double b, double *s, double *e) {
+    if (which == 0) quick_two_sum(a, b, s, e);
+    else if (which == 1) two_sum(a, b, s, e);
+    else two_prod(a, b, s, e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Elementwise add / mul and AXPY (the vector layer driven by the BF ops).   */
+/* ------------------------------------------------------------------------ */
+
+void orc_add(int K, int64_t n, const double *x, int64_t psx, const double *y,
+             int64_t psy, double *z, int64_t psz) {
+    for (int64_t i = 0; i < n; i++) {
+        double a[4], b[4], c[4];
+        gather(K, x, psx, i, a);
+        gather(K, y, psy, i, b);
+        mp_add(K, a, b, c);
+        scatter(K, z, psz, i, c);
+    }
+}
+void orc_mul(int K, int64_t n, const double *x, int64_t psx, const double *y,
+             int64_t psy, double *z, int64_t psz) {
+    for (int64_t i = 0; i < n; i++) {
+        double a[4], b[4], c[4];
+        gather(K, x, psx, i, a);
+        gather(K, y, psy, i, b);
+        mp_mul(K, a, b, c);
+        scatter(K, z, psz, i, c);
+    }
+}
+/* y_i := alpha * x_i + y_i : one BF multiplication, then one BF addition. */
+void orc_axpy(int K, int64_t n, const double *alpha, const double *x, int64_t psx,
+              double *y, int64_t psy) {
+    for (int64_t i = 0; i < n; i++) {
+        double a[4], b[4], p[4], c[4];
+        gather(K, x, psx, i, a);
+        gather(K, y, psy, i, b);
+        mp_mul(K, alpha, a, p);
+        mp_add(K, p, b, c);
+        scatter(K, y, psy, i, c);
+    }
+}
+
+/* Dot product by its definition: acc = 0; acc := acc + x_i*y_i, i ascending. */
+void orc_dot(int K, int64_t n, const double *x, int64_t psx, const double *y,
+             int64_t psy, double *r) {
+    double acc[4], a[4], b[4], p[4];
+    mp_zero(K, acc);
+    for (int64_t i = 0; i < n; i++) {
+        gather(K, x, psx, i, a);
+        gather(K, y, psy, i, b);
+        mp_mul(K, a, b, p);
+        mp_add(K, acc, p, acc);
+    }
+    memcpy(r, acc, sizeof(double) * K);
+}
+
+/* y := op(A) x with A an m x n row-major matrix; op(A) = A (trans = 0) or
+ * A^T (trans = 1).  Each output is a sequential dot product. */
+void orc_gemv(int K, int trans, int64_t m, int64_t n, const double *A, int64_t lda,
+              int64_t psA, const double *x, int64_t psx, double *y, int64_t psy) {
+    int64_t rows = trans ? n : m, len = trans ? m : n;
+    for (int64_t r = 0; r < rows; r++) {
+        double acc[4], a[4], b[4], p[4];
+        mp_zero(K, acc);
+        for (int64_t l = 0; l < len; l++) {
+            int64_t idx = trans ? (l * lda + r) : (r * lda + l);
+            gather(K, A, psA, idx, a);
+            gather(K, x, psx, l, b);
+            mp_mul(K, a, b, p);
+            mp_add(K, acc, p, acc);
+        }
+        scatter(K, y, psy, r, acc);
+    }
+}
+
+/* One entry of C = op(A) op(B) by the naive triple loop (Section 3.1): the
+ * k index ascends, each step one BF multiplication and one BF addition. */
+static void gemm_entry(int K, int tA, int tB, int64_t i, int64_t j, int64_t k,
+                       const double *A, int64_t lda, int64_t psA, const double *B,
+                       int64_t ldb, int64_t psB, double *acc) {
+    double a[4], b[4], p[4];
+    mp_zero(K, acc);
+    for (int64_t l = 0; l < k; l++) {
+        gather(K, A, psA, tA ? (l * lda + i) : (i * lda + l), a);
+        gather(K, B, psB, tB ? (j * ldb + l) : (l * ldb + j), b);
+        mp_mul(K, a, b, p);
+        mp_add(K, acc, p, acc);
+    }
+}
+
+void orc_gemm(int K, int tA, int tB, int64_t m, int64_t n, int64_t k, const double *A,
+              int64_t lda, int64_t psA, const double *B, int64_t ldb, int64_t psB,
+              double *C, int64_t ldc, int64_t psC) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; i++) {
+        for (int64_t j = 0; j < n; j++) {
+            double acc[4];
+            gemm_entry(K, tA, tB, i, j, k, A, lda, psA, B, ldb, psB, acc);
+            scatter(K, C, psC, i * ldc + j, acc);
+        }
+    }
+}
+
+/* Selected entries (rows[t], cols[t]) of op(A) op(B); out is K x cnt planes. */
+void orc_gemm_entries(int K, int tA, int tB, int64_t k, const double *A, int64_t lda,
+                      int64_t psA, const double *B, int64_t ldb, int64_t psB,
+                      int64_t cnt, const int64_t *rows, const int64_t *cols,
+                      double *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < cnt; t++) {
+        double acc[4];
+        gemm_entry(K, tA, tB, rows[t], cols[t], k, A, lda, psA, B, ldb, psB, acc);
+        scatter(K, out, cnt, t, acc);
+    }
+}
+
+/* ---- float-float (binary32 double-word) versions of the same layer ---- */
+
+void orc_ff_add(int64_t n, const float *x, int64_t psx, const float *y, int64_t psy,
+                float *z, int64_t psz) {
+    for (int64_t i = 0; i < n; i++) {
+        float a[2] = {x[i], x[psx + i]}, b[2] = {y[i], y[psy + i]}, c[2];
+        ff_bf_add(a, b, c);
+        z[i] = c[0]; z[psz + i] = c[1];
+    }
+}
+void orc_ff_mul(int64_t n, const float *x, int64_t psx, const float *y, int64_t psy,
+                float *z, int64_t psz) {
+    for (int64_t i = 0; i < n; i++) {
+        float a[2] = {x[i], x[psx + i]}, b[2] = {y[i], y[psy + i]}, c[2];
+        ff_bf_mul(a, b, c);
+        z[i] = c[0]; z[psz + i] = c[1];
+    }
+}
+void orc_ff_axpy(int64_t n, const float *alpha, const float *x, int64_t psx, float *y,
+                 int64_t psy) {
+    for (int64_t i = 0; i < n; i++) {
+        float a[2] = {x[i], x[psx + i]}, b[2] = {y[i], y[psy + i]}, p[2], c[2];
+        ff_bf_mul(alpha, a, p);
+        ff_bf_add(p, b, c);
+        y[i] = c[0]; y[psy + i] = c[1];
+    }
+}
+void orc_ff_dot(int64_t n, const float *x, int64_t psx, const float *y, int64_t psy,
+                float *r) {
+    float acc[2] = {0.0f, 0.0f};
+    for (int64_t i = 0; i < n; i++) {
+        float a[2] = {x[i], x[psx + i]}, b[2] = {y[i], y[psy + i]}, p[2];
+        ff_bf_mul(a, b, p);
+        ff_bf_add(acc, p, acc);
+    }
+    r[0] = acc[0]; r[1] = acc[1];
+}
+void orc_ff_gemv(int trans, int64_t m, int64_t n, const float *A, int64_t lda,
+                 int64_t psA, const float *x, int64_t psx, float *y, int64_t psy) {
+    int64_t rows = trans ? n : m, len = trans ? m : n;
+    for (int64_t r = 0; r < rows; r++) {
+        float acc[2] = {0.0f, 0.0f};
+        for (int64_t l = 0; l < len; l++) {
+            int64_t idx = trans ? (l * lda + r) : (r * lda + l);
+            float a[2] = {A[idx], A[psA + idx]}, b[2] = {x[l], x[psx + l]}, p[2];
+            ff_bf_mul(a, b, p);
+            ff_bf_add(acc, p, acc);
+        }
+        y[r] = acc[0]; y[psy + r] = acc[1];
+    }
+}
+static void ff_gemm_entry(int tA, int tB, int64_t i, int64_t j, int64_t k,
+                          const float *A, int64_t lda, int64_t psA, const float *B,
+                          int64_t ldb, int64_t psB, float *acc) {
+    acc[0] = acc[1] = 0.0f;
+    for (int64_t l = 0; l < k; l++) {
+        int64_t ia = tA ? (l * lda + i) : (i * lda + l);
+        int64_t ib = tB ? (j * ldb + l) : (l * ldb + j);
+        float a[2] = {A[ia], A[psA + ia]}, b[2] = {B[ib], B[psB + ib]}, p[2];
+        ff_bf_mul(a, b, p);
+        ff_bf_add(acc, p, acc);
+    }
+}
+void orc_ff_gemm(int tA, int tB, int64_t m, int64_t n, int64_t k, const float *A,
+                 int64_t lda, int64_t psA, const float *B, int64_t ldb, int64_t psB,
+                 float *C, int64_t ldc, int64_t psC) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t j = 0; j < n; j++) {
+            float acc[2];
+            ff_gemm_entry(tA, tB, i, j, k, A, lda, psA, B, ldb, psB, acc);
+            C[i * ldc + j] = acc[0]; C[psC + i * ldc + j] = acc[1];
+        }
+}
+void orc_ff_gemm_entries(int tA, int tB, int64_t k, const float *A, int64_t lda,
+                         int64_t psA, const float *B, int64_t ldb, int64_t psB,
+                         int64_t cnt, const int64_t *rows, const int64_t *cols,
+                         float *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < cnt; t++) {
+        float acc[2];
+        ff_gemm_entry(tA, tB, rows[t], cols[t], k, A, lda, psA, B, ldb, psB, acc);
+        out[t] = acc[0]; out[cnt + t] = acc[1];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real polynomial evaluation by Horner's method (Section 4.1) and its       */
+/* reverse-mode derivative.                                                  */
+/* Coefficients of polynomial b: a_i at coef[c*psc + b*(deg+1) + i].         */
+/* ------------------------------------------------------------------------ */
+
+/* p(x) = sum_i a_i x^i:  h = a_deg;  h := h*x + a_i for i = deg-1 .. 0. */
+void orc_polyval(int K, int64_t batch, int64_t deg, const double *coef, int64_t psc,
+                 const double *x, int64_t psx, double *y, int64_t psy) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < batch; b++) {
+        const int64_t off = b * (deg + 1);
+        double h[4], xv[4], a[4];
+        gather(K, x, psx, b, xv);
+        gather(K, coef, psc, off + deg, h);
+        for (int64_t i = deg - 1; i >= 0; i--) {
+            gather(K, coef, psc, off + i, a);
+            mp_mul(K, h, xv, h);
+            mp_add(K, h, a, h);
+        }
+        scatter(K, y, psy, b, h);
+    }
+}
+
+/* Gradients of L = sum_b g_b p_b(x_b):
+ *   dL/da_{b,i} = g_b x_b^i, by the adjoint of the Horner recurrence
+ *                 (t = g_b; t := t*x_b per step, i ascending);
+ *   dL/dx_b     = g_b p_b'(x_b), with p' from the derivative Horner
+ *                 recurrence d := d*x + h (before h := h*x + a_i), d = 0 at start.
+ * Either output pointer may be NULL. */
+void orc_polyval_backward(int K, int64_t batch, int64_t deg, const double *coef,
+                          int64_t psc, const double *x, int64_t psx, const double *g,
+                          int64_t psg, double *gcoef, int64_t psgc, double *gx,
+                          int64_t psgx) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < batch; b++) {
+        const int64_t off = b * (deg + 1);
+        double xv[4], gv[4], t[4];
+        gather(K, x, psx, b, xv);
+        gather(K, g, psg, b, gv);
+        if (gcoef) {
+            memcpy(t, gv, sizeof(double) * K);
+            scatter(K, gcoef, psgc, off, t);
+            for (int64_t i = 1; i <= deg; i++) {
+                mp_mul(K, t, xv, t);
+                scatter(K, gcoef, psgc, off + i, t);
+            }
+        }
+        if (gx) {
+            double h[4], d[4], a[4], r[4];
+            mp_zero(K, d);
+            gather(K, coef, psc, off + deg, h);
+            for (int64_t i = deg - 1; i >= 0; i--) {
+                gather(K, coef, psc, off + i, a);
+                mp_mul(K, d, xv, d);
+                mp_add(K, d, h, d);
+                mp_mul(K, h, xv, h);
+                mp_add(K, h, a, h);
+            }
+            mp_mul(K, gv, d, r);
+            scatter(K, gx, psgx, b, r);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Complex multicomponent numbers, division via Newton's method (Section 2   */
+/* says division is built from addition and multiplication by Newton's      */
+/* method; the iteration below is the classical reciprocal iteration).       */
+/* A complex number is two K-component numbers re[], im[].                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double re[4], im[4]; } cmp;
+
+/* (a+bi)(c+di) = (ac - bd) + (ad + bc) i, four BF products, two BF sums. */
+static void cmp_mul(int K, const cmp *x, const cmp *y, cmp *z) {
+    double ac[4], bd[4], ad[4], bc[4];
+    cmp r;
+    mp_mul(K, x->re, y->re, ac);
+    mp_mul(K, x->im, y->im, bd);
+    mp_mul(K, x->re, y->im, ad);
+    mp_mul(K, x->im, y->re, bc);
+    mp_sub(K, ac, bd, r.re);
+    mp_add(K, ad, bc, r.im);
+    *z = r;
+}
+static void cmp_add(int K, const cmp *x, const cmp *y, cmp *z) {
+    mp_add(K, x->re, y->re, z->re);
+    mp_add(K, x->im, y->im, z->im);
+}
+static void cmp_sub(int K, const cmp *x, const cmp *y, cmp *z) {
+    mp_sub(K, x->re, y->re, z->re);
+    mp_sub(K, x->im, y->im, z->im);
+}
+
+/* Newton iterations for the reciprocal (doubling the correct bits each
+ * time): y0 = 1/d_0 in binary64; DD needs one step, TD and QD two. */
+static int newton_steps(int K) { return K == 2 ? 1 : 2; }
+static void mp_recip(int K, const double *d, double *y) {
+    double one[4], p[4], e[4], ye[4];
+    mp_set_d(K, 1.0, one);
+    mp_set_d(K, 1.0 / d[0], y);
+    for (int it = 0; it < newton_steps(K); it++) {
+        mp_mul(K, d, y, p);
+        mp_sub(K, one, p, e);        /* e = 1 - d*y */
+        mp_mul(K, y, e, ye);
+        mp_add(K, y, ye, y);         /* y = y + y*e */
+    }
+}
+void orc_recip(int K, const double *d, double *y) { mp_recip(K, d, y); }
+
+/* x / y = x * conj(y) * (1 / |y|^2). */
+static void cmp_div(int K, const cmp *x, const cmp *y, cmp *z) {
+    double rr[4], ii[4], den[4], inv[4], t1[4], t2[4], nr[4], ni[4];
+    mp_mul(K, y->re, y->re, rr);
+    mp_mul(K, y->im, y->im, ii);
+    mp_add(K, rr, ii, den);
+    mp_recip(K, den, inv);
+    mp_mul(K, x->re, y->re, t1);
+    mp_mul(K, x->im, y->im, t2);
+    mp_add(K, t1, t2, nr);          /* Re(x conj y) */
+    mp_mul(K, x->im, y->re, t1);
+    mp_mul(K, x->re, y->im, t2);
+    mp_sub(K, t1, t2, ni);          /* Im(x conj y) */
+    mp_mul(K, nr, inv, z->re);
+    mp_mul(K, ni, inv, z->im);
+}
+void orc_cdiv(int K, const double *xr, const double *xi, const double *yr,
+              const double *yi, double *zr, double *zi) {
+    cmp x, y, z;
+    memcpy(x.re, xr, 8 * K); memcpy(x.im, xi, 8 * K);
+    memcpy(y.re, yr, 8 * K); memcpy(y.im, yi, 8 * K);
+    cmp_div(K, &x, &y, &z);
+    memcpy(zr, z.re, 8 * K); memcpy(zi, z.im, 8 * K);
+}
+
+/* Exact power-of-two rescaling of a complex number so that the larger of its
+ * leading components lies in [0.5, 1); the scale goes into *E.  It changes
+ * no bits of the represented value beyond the exponent, so it only protects
+ * Horner and the root-difference product from binary64 overflow.
+ * down_only != 0 rescales only values of magnitude >= 1 (used by Horner, whose
+ * additive terms c_k 2^{-E} must never be scaled up into overflow). */
+static void cmp_rescale(int K, cmp *z, int64_t *E, int down_only) {
+    double m = fmax(fabs(z->re[0]), fabs(z->im[0]));
+    if (m == 0.0 || !isfinite(m)) return;
+    int e;
+    frexp(m, &e);
+    if (down_only && e < 1) return;
+    for (int c = 0; c < K; c++) {
+        z->re[c] = ldexp(z->re[c], -e);
+        z->im[c] = ldexp(z->im[c], -e);
+    }
+    *E += e;
+}
+static int clamp_exp(int64_t e) {
+    return e > 100000 ? 100000 : (e < -100000 ? -100000 : (int)e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Durand-Kerner (Weierstrass) simultaneous iteration, Section 4.2.          */
+/* ------------------------------------------------------------------------ */
+
+static void load_c(int K, const double *re, const double *im, int64_t ps, int64_t i,
+                   cmp *z) {
+    gather(K, re, ps, i, z->re);
+    gather(K, im, ps, i, z->im);
+}
+static void store_c(int K, double *re, double *im, int64_t ps, int64_t i,
+                    const cmp *z) {
+    scatter(K, re, ps, i, z->re);
+    scatter(K, im, ps, i, z->im);
+}
+
+/* Monic coefficients of q_n = p_n / a_n: c_i = a_i / a_n, i = 0..n-1. */
+static void dk_monic(int K, int64_t n, const double *are, const double *aim,
+                     int64_t psa, int64_t aoff, cmp *c) {
+    cmp an, ai;
+    load_c(K, are, aim, psa, aoff + n, &an);
+    for (int64_t i = 0; i < n; i++) {
+        load_c(K, are, aim, psa, aoff + i, &ai);
+        cmp_div(K, &ai, &an, &c[i]);
+    }
+}
+
+/* Aberth initial values (equation for z_i^(0)): centre -c_{n-1}/n, radius
+ * r = max_i |n_nz c_i|^(1/(n-i)), angles 2(i-1)pi/n + 3/(2n).  Evaluated in
+ * binary64 on the leading components; lower components start at zero. */
+static void dk_aberth(int K, int64_t n, const cmp *c, cmp *z) {
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (c[i].re[0] != 0.0 || c[i].im[0] != 0.0) nnz++;
+    double r = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double mag = hypot(c[i].re[0], c[i].im[0]) * (double)nnz;
+        double t = pow(mag, 1.0 / (double)(n - i));
+        if (t > r) r = t;
+    }
+    double cre = -c[n - 1].re[0] / (double)n;
+    double cim = -c[n - 1].im[0] / (double)n;
+    for (int64_t i = 0; i < n; i++) {
+        double th = 2.0 * (double)i * M_PI / (double)n + 3.0 / (2.0 * (double)n);
+        memset(&z[i], 0, sizeof(cmp));
+        z[i].re[0] = cre + r * cos(th);
+        z[i].im[0] = cim + r * sin(th);
+    }
+}
+
+/* q(z) by Horner on the monic coefficients, kept as value * 2^E with E >= 0:
+ * h = 1; h := h*z + c_k 2^{-E}, k = n-1 .. 0, rescaling h down after each step. */
+static void dk_horner(int K, int64_t n, const cmp *c, const cmp *z, cmp *h, int64_t *E) {
+    memset(h, 0, sizeof(cmp));
+    h->re[0] = 1.0;
+    *E = 0;
+    for (int64_t k = n - 1; k >= 0; k--) {
+        cmp t, ck;
+        cmp_mul(K, h, z, &t);
+        mp_ldexp(K, c[k].re, clamp_exp(-*E), ck.re);
+        mp_ldexp(K, c[k].im, clamp_exp(-*E), ck.im);
+        cmp_add(K, &t, &ck, h);
+        cmp_rescale(K, h, E, 1);
+    }
+}
+
+/* One Jacobi sweep: every new z_i is computed from the previous iterate:
+ *   z_i := z_i - q(z_i) / prod_{j != i} (z_i - z_j), j ascending. */
+static void dk_sweep(int K, int64_t n, const cmp *c, const cmp *z, cmp *znew) {
+    for (int64_t i = 0; i < n; i++) {
+        cmp q, P, d, w;
+        int64_t E, F = 0;
+        dk_horner(K, n, c, &z[i], &q, &E);
+        memset(&P, 0, sizeof(cmp));
+        P.re[0] = 1.0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            cmp_sub(K, &z[i], &z[j], &d);
+            cmp_mul(K, &P, &d, &P);
+            cmp_rescale(K, &P, &F, 0);
+        }
+        cmp_div(K, &q, &P, &w);
+        mp_ldexp(K, w.re, clamp_exp(E - F), w.re);
+        mp_ldexp(K, w.im, clamp_exp(E - F), w.im);
+        cmp_sub(K, &z[i], &w, &znew[i]);
+    }
+}
+
+/* Batched driver.  Polynomial b has degree deg[b]; its coefficients a_0..a_n
+ * start at coef_off[b], its roots at root_off[b].  flags bit 0: compute the
+ * Aberth start values first (otherwise the roots arrays hold the start).
+ * status[b] = 0 if all roots are finite after the iterations, 1 otherwise. */
+void orc_polyroots(int K, int64_t batch, const int32_t *deg, const int64_t *coef_off,
+                   const int64_t *root_off, const double *are, const double *aim,
+                   int64_t psc, double *zre, double *zim, int64_t psr, int iters,
+                   int flags, int32_t *status) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < batch; b++) {
+        int64_t n = deg[b];
+        cmp *c = (cmp *)calloc((size_t)n, sizeof(cmp));
+        cmp *z = (cmp *)calloc((size_t)n, sizeof(cmp));
+        cmp *zn = (cmp *)calloc((size_t)n, sizeof(cmp));
+        dk_monic(K, n, are, aim, psc, coef_off[b], c);
+        if (flags & 1) dk_aberth(K, n, c, z);
+        else
+            for (int64_t i = 0; i < n; i++) load_c(K, zre, zim, psr, root_off[b] + i, &z[i]);
+        for (int it = 0; it < iters; it++) {
+            dk_sweep(K, n, c, z, zn);
+            cmp *t = z; z = zn; zn = t;
+        }
+        int bad = 0;
+        for (int64_t i = 0; i < n; i++) {
+            for (int q = 0; q < K; q++)
+                if (!isfinite(z[i].re[q]) || !isfinite(z[i].im[q])) bad = 1;
+            store_c(K, zre, zim, psr, root_off[b] + i, &z[i]);
+        }
+        if (status) status[b] = bad;
+        free(c); free(z); free(zn);
+    }
+}
+
+/* Monic coefficients alone (for tests of the division step). */
+void orc_dk_monic(int K, int64_t n, const double *are, const double *aim, int64_t psa,
+                  double *cre, double *cim, int64_t psc) {
+    cmp *c = (cmp *)calloc((size_t)n, sizeof(cmp));
+    dk_monic(K, n, are, aim, psa, 0, c);
+    for (int64_t i = 0; i < n; i++) store_c(K, cre, cim, psc, i, &c[i]);
+    free(c);
+}
+
+/* q(z) at given points (value and binary exponent), for residual tests. */
+void orc_dk_horner(int K, int64_t n, const double *cre, const double *cim, int64_t psc,
+                   int64_t npts, const double *zr, const double *zi, int64_t psz,
+                   double *qr, double *qi, int64_t psq, int64_t *E) {
+    cmp *c = (cmp *)calloc((size_t)n, sizeof(cmp));
+    for (int64_t i = 0; i < n; i++) load_c(K, cre, cim, psc, i, &c[i]);
+    for (int64_t t = 0; t < npts; t++) {
+        cmp z, q;
+        load_c(K, zr, zi, psz, t, &z);
+        dk_horner(K, n, c, &z, &q, &E[t]);
+        store_c(K, qr, qi, psq, t, &q);
+    }
+    free(c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ozaki-style error-free splitting of DD matrices and the slice GEMM.       */
+/* The paper only names the Ozaki scheme among its GEMM schemes (Section     */
+/* 3.1); the reading implemented here:                                       */
+/*  * row i of A gets the exponent e_i with max_l |A_il[0]| < 2^{e_i}        */
+/*    (frexp of the maximum; e_i = 0 for an all-zero row); column j of B     */
+/*    gets f_j the same way;                                                 */
+/*  * slice p = 1..s of an element (r1, r2) = (hi, lo) is the integer        */
+/*    m_p = rint(r1 * 2^{p*beta - e}), then (r1, r2) := TwoSum(r1 - m_p *    */
+/*    2^{e - p*beta}, r2): the residual stays exact;                          */
+/*  * level g = p + q collects sum_{p+q=g} sum_{l in block} mA_p mB_q in one */
+/*    binary64 accumulator, exact because every term is an integer and      */
+/*    kblk * (g-1) * 2^{2 beta} < 2^53;                                      */
+/*  * C_ij = sum over k-blocks (ascending), levels g = 2..s+1 (ascending) of */
+/*    DWBFAdd(acc, (S_g * 2^{e_i + f_j - g*beta}, 0)).                       */
+/* ------------------------------------------------------------------------ */
+
+static int exp_of_max(double m) {
+    if (m == 0.0) return 0;
+    int e;
+    frexp(m, &e);
+    return e;
+}
+
+/* Split one DD value into s integer-valued slices with exponent e. */
+static void split_value(double hi, double lo, int e, int s, int beta, double *m) {
+    double r1 = hi, r2 = lo;
+    for (int p = 1; p <= s; p++) {
+        double q = rint(ldexp(r1, p * beta - e));
+        double d = r1 - ldexp(q, e - p * beta);
+        two_sum(d, r2, &r1, &r2);
+        m[p - 1] = q;
+    }
+}
+
+/* Row exponents and slices of A (m x k, row-major, DD planes): slices are
+ * written as s planes of m x k (plane stride m*k). */
+void orc_ozaki_split_rows(int64_t m, int64_t k, const double *A, int64_t lda,
+                          int64_t psA, int s, int beta, int32_t *e_row,
+                          double *slices) {
+    for (int64_t i = 0; i < m; i++) {
+        double mx = 0.0;
+        for (int64_t l = 0; l < k; l++) mx = fmax(mx, fabs(A[i * lda + l]));
+        int e = exp_of_max(mx);
+        e_row[i] = e;
+        for (int64_t l = 0; l < k; l++) {
+            double sl[64];
+            split_value(A[i * lda + l], A[psA + i * lda + l], e, s, beta, sl);
+            for (int p = 0; p < s; p++) slices[(int64_t)p * m * k + i * k + l] = sl[p];
+        }
+    }
+}
+/* Column exponents and slices of B (k x n, row-major, DD planes): s planes of
+ * k x n. */
+void orc_ozaki_split_cols(int64_t k, int64_t n, const double *B, int64_t ldb,
+                          int64_t psB, int s, int beta, int32_t *f_col,
+                          double *slices) {
+    for (int64_t j = 0; j < n; j++) {
+        double mx = 0.0;
+        for (int64_t l = 0; l < k; l++) mx = fmax(mx, fabs(B[l * ldb + j]));
+        int f = exp_of_max(mx);
+        f_col[j] = f;
+        for (int64_t l = 0; l < k; l++) {
+            double sl[64];
+            split_value(B[l * ldb + j], B[psB + l * ldb + j], f, s, beta, sl);
+            for (int p = 0; p < s; p++) slices[(int64_t)p * k * n + l * n + j] = sl[p];
+        }
+    }
+}
+
+/* Entries (rows[t], cols[t]) of the Ozaki DD product, from split operands. */
+void orc_ozaki_entries(int64_t m, int64_t n, int64_t k, int s, int beta, int64_t kblk,
+                       const int32_t *e_row, const double *sa, const int32_t *f_col,
+                       const double *sb, int64_t cnt, const int64_t *rows,
+                       const int64_t *cols, double *out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < cnt; t++) {
+        int64_t i = rows[t], j = cols[t];
+        double acc[2] = {0.0, 0.0};
+        for (int64_t l0 = 0; l0 < k; l0 += kblk) {
+            int64_t l1 = l0 + kblk < k ? l0 + kblk : k;
+            for (int g = 2; g <= s + 1; g++) {
+                double S = 0.0;
+                for (int p = 1; p < g; p++) {
+                    int q = g - p;
+                    if (p > s || q > s) continue;
+                    for (int64_t l = l0; l < l1; l++)
+                        S += sa[(int64_t)(p - 1) * m * k + i * k + l] *
+                             sb[(int64_t)(q - 1) * k * n + l * n + j];
+                }
+                double term[2] = {ldexp(S, e_row[i] + f_col[j] - g * beta), 0.0};
+                dw_bf_add(acc, term, acc);
+            }
+        }
+        out[t] = acc[0];
+        out[cnt + t] = acc[1];
+    }
+}

@@ -1,0 +1,353 @@
+// mpx_gemm.hip -- C := op(A) op(B) in DD / TD / QD / FF on gfx950.
+//
+// The product of Section 3.1 (benchmarked there with the branch-free TD and
+// QD operations) is the dominant kernel.  Its multiply-add is 29 / 96 / 209
+// FP64 VALU instructions (DD / TD / QD, Tables 1-2 plus the DW algorithms)
+// against 2K operand doubles, so it is bound by FP64 VALU issue, not by
+// memory, and the MFMA units cannot help (the BF operations are not dot
+// products).  The design therefore maximises VALU issue:
+//
+//  * a 256-thread workgroup (four wave64s) owns a BM x BN tile of C, each
+//    thread a TM x TN register micro-tile of K-component accumulators; the
+//    independent accumulators give the scheduler TM*TN interleavable MAC
+//    chains per thread;
+//  * per k-panel of depth BK the workgroup stages the K component planes of
+//    the A and B panels in LDS (sA[c][kk][row], sB[c][kk][col]); a thread
+//    reads its rows ty + 16 i (wave-uniform broadcasts) and columns
+//    tx + 16 j (16 consecutive doubles per wave: conflict-free);
+//  * the next panel is fetched from global memory into registers while the
+//    current one is consumed (one-deep software pipeline);
+//  * every C_ij is accumulated in ascending l from zero, exactly the naive
+//    triple loop's sequence, so results are bit-identical for every tiling.
+//
+// Workgroups are numbered so that the eight XCDs (which receive workgroups
+// round-robin) each get a contiguous band of tile rows: tiles that share an
+// A panel share an L2.
+#include "mp_arith.hpp"
+#include "mpx_internal.hpp"
+
+#include <mutex>
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace mpx {
+
+constexpr int kGemmThreads = 256;
+
+template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
+       const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
+       long long ldc, long long psC, int tiles_n, int tiles_total) {
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    constexpr int A_PER = (BM * BK + kGemmThreads - 1) / kGemmThreads;
+    constexpr int B_PER = (BN * BK + kGemmThreads - 1) / kGemmThreads;
+    __shared__ T sA[K][BK][BM];
+    __shared__ T sB[K][BK][BN];
+
+    // XCD-aware tile order: workgroup w runs on XCD w % 8; give each XCD a
+    // contiguous range of tile ids (row-major over the tile grid).
+    const int w = blockIdx.x;
+    const int per_xcd = (tiles_total + 7) / 8;
+    const int xcd = w % 8, slot = w / 8;
+    int tile = xcd * per_xcd + slot;
+    if (per_xcd * 8 != tiles_total) tile = w;  // uneven split: plain order
+    const int m0 = (tile / tiles_n) * BM;
+    const int n0 = (tile % tiles_n) * BN;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+
+    mpn<T, K> acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mp_zero<T, K>();
+
+    T ra[A_PER][K], rb[B_PER][K];
+
+    // Fetch the panel starting at k0 into registers (zero outside the matrix).
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < A_PER; ++t) {
+            const int e = tid + t * kGemmThreads;
+            int r, kk;
+            if (TA) { kk = e / BM; r = e % BM; } else { r = e / BK; kk = e % BK; }
+            const int gr = m0 + r, gk = k0 + kk;
+            const bool ok = e < BM * BK && gr < m && gk < k;
+            const long long idx = TA ? (long long)gk * lda + gr : (long long)gr * lda + gk;
+#pragma unroll
+            for (int c = 0; c < K; ++c) ra[t][c] = ok ? A[c * psA + idx] : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < B_PER; ++t) {
+            const int e = tid + t * kGemmThreads;
+            int cc, kk;
+            if (TB) { cc = e / BK; kk = e % BK; } else { kk = e / BN; cc = e % BN; }
+            const int gc = n0 + cc, gk = k0 + kk;
+            const bool ok = e < BN * BK && gc < n && gk < k;
+            const long long idx = TB ? (long long)gc * ldb + gk : (long long)gk * ldb + gc;
+#pragma unroll
+            for (int c = 0; c < K; ++c) rb[t][c] = ok ? B[c * psB + idx] : T(0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int t = 0; t < A_PER; ++t) {
+            const int e = tid + t * kGemmThreads;
+            if (e < BM * BK) {
+                int r, kk;
+                if (TA) { kk = e / BM; r = e % BM; } else { r = e / BK; kk = e % BK; }
+#pragma unroll
+                for (int c = 0; c < K; ++c) sA[c][kk][r] = ra[t][c];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < B_PER; ++t) {
+            const int e = tid + t * kGemmThreads;
+            if (e < BN * BK) {
+                int cc, kk;
+                if (TB) { cc = e / BK; kk = e % BK; } else { kk = e / BN; cc = e % BN; }
+#pragma unroll
+                for (int c = 0; c < K; ++c) sB[c][kk][cc] = rb[t][c];
+            }
+        }
+    };
+    auto mac_step = [&](int kk) {
+        mpn<T, K> a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int c = 0; c < K; ++c) a[i].c[c] = sA[c][kk][ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int c = 0; c < K; ++c) b[j].c[c] = sB[c][kk][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = bf_add(acc[i][j], bf_mul(a[i], b[j]));
+    };
+
+    if (k > 0) fetch(0);
+    for (int k0 = 0; k0 < k; k0 += BK) {
+        __syncthreads();  // previous panel fully consumed
+        stash();
+        __syncthreads();
+        if (k0 + BK < k) fetch(k0 + BK);  // overlaps the MACs below
+        const int kend = k - k0;
+        if (kend >= BK) {
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk) mac_step(kk);
+        } else {
+            for (int kk = 0; kk < kend; ++kk) mac_step(kk);
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int r = m0 + ty + 16 * i;
+        if (r >= m) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int cidx = n0 + tx + 16 * j;
+            if (cidx < n) mp_store<T, K>(C, psC, (long long)r * ldc + cidx, acc[i][j]);
+        }
+    }
+}
+
+// ----------------------------------------------------------- variants ----
+
+struct GemmArgs {
+    int m, n, k, tA, tB;
+    const void* A; long long lda, psA;
+    const void* B; long long ldb, psB;
+    void* C; long long ldc, psC;
+};
+
+template <typename T, int K, int TM, int TN, int BK>
+static int run_variant(const GemmArgs& g, hipStream_t s) {
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    const int tn = (int)ceil_div(g.n, BN), tm = (int)ceil_div(g.m, BM);
+    const int total = tn * tm;
+    if (total == 0) return MPX_OK;
+#define MPX_GEMM_LAUNCH(TA_, TB_)                                                           \
+    k_gemm<T, K, TM, TN, BK, TA_, TB_><<<total, kGemmThreads, 0, s>>>(                      \
+        g.m, g.n, g.k, (const T*)g.A, g.lda, g.psA, (const T*)g.B, g.ldb, g.psB, (T*)g.C,   \
+        g.ldc, g.psC, tn, total)
+    if (!g.tA && !g.tB) MPX_GEMM_LAUNCH(false, false);
+    else if (g.tA && !g.tB) MPX_GEMM_LAUNCH(true, false);
+    else if (!g.tA && g.tB) MPX_GEMM_LAUNCH(false, true);
+    else MPX_GEMM_LAUNCH(true, true);
+#undef MPX_GEMM_LAUNCH
+    return launch_status();
+}
+
+using VariantFn = int (*)(const GemmArgs&, hipStream_t);
+
+struct Variant {
+    VariantFn fn;
+    int bm, bn;
+    const char* name;
+};
+
+// Candidate micro-tiles per precision (index 0 = largest tile).
+static const std::vector<Variant>& variants(int prec) {
+    static const std::vector<Variant> dd = {
+        {run_variant<double, 2, 4, 4, 8>, 64, 64, "dd_4x4_k8"},
+        {run_variant<double, 2, 2, 4, 8>, 32, 64, "dd_2x4_k8"},
+        {run_variant<double, 2, 2, 2, 16>, 32, 32, "dd_2x2_k16"},
+    };
+    static const std::vector<Variant> td = {
+        {run_variant<double, 3, 2, 4, 8>, 32, 64, "td_2x4_k8"},
+        {run_variant<double, 3, 2, 2, 8>, 32, 32, "td_2x2_k8"},
+        {run_variant<double, 3, 1, 2, 16>, 16, 32, "td_1x2_k16"},
+    };
+    static const std::vector<Variant> qd = {
+        {run_variant<double, 4, 2, 2, 8>, 32, 32, "qd_2x2_k8"},
+        {run_variant<double, 4, 1, 2, 16>, 16, 32, "qd_1x2_k16"},
+        {run_variant<double, 4, 1, 1, 16>, 16, 16, "qd_1x1_k16"},
+    };
+    static const std::vector<Variant> ff = {
+        {run_variant<float, 2, 4, 4, 8>, 64, 64, "ff_4x4_k8"},
+        {run_variant<float, 2, 2, 4, 8>, 32, 64, "ff_2x4_k8"},
+        {run_variant<float, 2, 2, 2, 16>, 32, 32, "ff_2x2_k16"},
+    };
+    static const std::vector<Variant> none;
+    switch (prec) {
+        case MPX_DD: return dd;
+        case MPX_TD: return td;
+        case MPX_QD: return qd;
+        case MPX_FF: return ff;
+        default: return none;
+    }
+}
+
+// Tuned choices, keyed by (prec, tA, tB, log2 buckets of m, n, k).
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+
+static int ilog2_bucket(long long v) {
+    int b = 0;
+    while ((1LL << (b + 1)) <= v) ++b;
+    return b;
+}
+static TuneKey tune_key(int prec, const GemmArgs& g) {
+    return TuneKey(prec, g.tA, g.tB, ilog2_bucket(g.m), ilog2_bucket(g.n), ilog2_bucket(g.k));
+}
+
+// Untuned default: the largest tile that still yields at least 2048
+// workgroups (8 per CU), else the smallest tile.
+static int default_variant(int prec, const GemmArgs& g) {
+    const auto& v = variants(prec);
+    for (size_t i = 0; i < v.size(); ++i) {
+        const long long wg = ceil_div(g.m, v[i].bm) * ceil_div(g.n, v[i].bn);
+        if (wg >= 2048) return (int)i;
+    }
+    return (int)v.size() - 1;
+}
+
+static int pick_variant(int prec, const GemmArgs& g) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(prec, g));
+    return it != g_tune.end() ? it->second : default_variant(prec, g);
+}
+
+static int check_gemm(int prec, int tA, int tB, int64_t m, int64_t n, int64_t k, const void* A,
+                      int64_t lda, int64_t psA, const void* B, int64_t ldb, int64_t psB,
+                      const void* C, int64_t ldc, int64_t psC) {
+    if (!prec_k(prec)) return MPX_EPREC;
+    if (m < 0 || n < 0 || k < 0 || (tA != 0 && tA != 1) || (tB != 0 && tB != 1))
+        return MPX_EINVAL;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return MPX_ENOTSUP;
+    const int64_t ar = tA ? k : m, ac = tA ? m : k;  // stored shape of A
+    const int64_t br = tB ? n : k, bc = tB ? k : n;  // stored shape of B
+    if (ar > 0 && ac > 0 && (A == nullptr || lda < ac || psA < (ar - 1) * lda + ac)) return MPX_EINVAL;
+    if (br > 0 && bc > 0 && (B == nullptr || ldb < bc || psB < (br - 1) * ldb + bc)) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (C == nullptr || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
+    return MPX_OK;
+}
+
+}  // namespace mpx
+
+using namespace mpx;
+
+extern "C" int mpx_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k,
+                        const void* A, int64_t lda, int64_t psA, const void* B, int64_t ldb,
+                        int64_t psB, void* C, int64_t ldc, int64_t psC, void* stream) {
+    int st = check_gemm(prec, transA, transB, m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC);
+    if (st) return st;
+    if (m == 0 || n == 0) return MPX_OK;
+    GemmArgs g{(int)m, (int)n, (int)k, transA, transB, A, lda, psA, B, ldb, psB, C, ldc, psC};
+    return variants(prec)[pick_variant(prec, g)].fn(g, as_stream(stream));
+}
+
+// Number of kernel variants available for a precision, and their names.
+extern "C" int mpx_gemm_variant_count(int prec) { return (int)variants(prec).size(); }
+
+extern "C" const char* mpx_gemm_variant_name(int prec, int v) {
+    const auto& vs = variants(prec);
+    return (v >= 0 && v < (int)vs.size()) ? vs[v].name : nullptr;
+}
+
+// Run one specific variant (used by the autotuner and by tests that check
+// that every tiling produces identical bits).
+extern "C" int mpx_gemm_variant(int prec, int variant, int transA, int transB, int64_t m,
+                                int64_t n, int64_t k, const void* A, int64_t lda, int64_t psA,
+                                const void* B, int64_t ldb, int64_t psB, void* C, int64_t ldc,
+                                int64_t psC, void* stream) {
+    int st = check_gemm(prec, transA, transB, m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC);
+    if (st) return st;
+    if (variant < 0 || variant >= (int)variants(prec).size()) return MPX_EINVAL;
+    if (m == 0 || n == 0) return MPX_OK;
+    GemmArgs g{(int)m, (int)n, (int)k, transA, transB, A, lda, psA, B, ldb, psB, C, ldc, psC};
+    return variants(prec)[variant].fn(g, as_stream(stream));
+}
+
+// Autotuner: time every variant `reps` times on the caller's buffers (C is
+// overwritten) with HIP events on `stream`, remember the fastest for this
+// (precision, transposes, size bucket), and return its index.  Synchronises
+// the stream; not capture-safe.
+extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, int64_t n,
+                                 int64_t k, const void* A, int64_t lda, int64_t psA,
+                                 const void* B, int64_t ldb, int64_t psB, void* C, int64_t ldc,
+                                 int64_t psC, int reps, float* best_ms, void* stream) {
+    int st = check_gemm(prec, transA, transB, m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC);
+    if (st) return st;
+    if (m == 0 || n == 0 || reps < 1) return MPX_EINVAL;
+    GemmArgs g{(int)m, (int)n, (int)k, transA, transB, A, lda, psA, B, ldb, psB, C, ldc, psC};
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPX_EDEVICE;
+    const auto& vs = variants(prec);
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < (int)vs.size(); ++v) {
+        if ((st = vs[v].fn(g, s))) break;  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !st; ++r) st = vs[v].fn(g, s);
+        hipEventRecord(e1, s);
+        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(prec, g)] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return best;
+}
+
+// Forget all tuned choices (back to the size heuristic).
+extern "C" void mpx_gemm_autotune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}

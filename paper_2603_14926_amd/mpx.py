@@ -1,0 +1,258 @@
+"""Python binding of libmpx (argument marshalling only).
+
+Multicomponent tensors are torch tensors on the GPU whose FIRST axis is the
+component: (K, n) vectors, (K, rows, cols) row-major matrices; dtype float64
+for DD / TD / QD (K = 2 / 3 / 4) and float32 for FF (K = 2).  Every function
+here validates shapes, picks pointers and strides, and calls the C ABI
+declared in include/mpx.h on torch's current stream; all arithmetic runs in
+the HIP kernels of libmpx.so.  There is no fallback: if the library is
+missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpx.so")
+
+DD, TD, QD, FF = 2, 3, 4, 0x102
+PRECS = {"dd": DD, "td": TD, "qd": QD, "ff": FF}
+_K = {DD: 2, TD: 3, QD: 4, FF: 2}
+
+OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI = 1, 2, 3, 4
+
+_lib = None
+
+
+class MpxError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libmpx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MpxError(f"{LIB_PATH} not found: build it with `python -m paper_2603_14926_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+_i = C.c_int
+_l = C.c_int64
+_v = C.c_void_p
+_z = C.c_size_t
+
+
+def _declare(L):
+    def sig(name, res, *args):
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = list(args)
+    sig("mpx_version", _i)
+    sig("mpx_status_string", C.c_char_p, _i)
+    sig("mpx_add", _i, _i, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_mul", _i, _i, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_axpy", _i, _i, _l, _v, _v, _l, _v, _l, _v)
+    sig("mpx_workspace_size", _z, _i, _i, _l, _l, _l, _l)
+    sig("mpx_dot", _i, _i, _l, _v, _l, _v, _l, _v, _v, _z, _v)
+    sig("mpx_gemv", _i, _i, _i, _l, _l, _v, _l, _l, _v, _l, _v, _l, _v, _z, _v)
+    sig("mpx_gemm", _i, _i, _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _v)
+    sig("mpx_gemm_variant", _i, _i, _i, _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _v)
+    sig("mpx_gemm_variant_count", _i, _i)
+    sig("mpx_gemm_variant_name", C.c_char_p, _i, _i)
+    sig("mpx_gemm_autotune", _i, _i, _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i,
+        C.POINTER(C.c_float), _v)
+    sig("mpx_gemm_autotune_reset", None)
+    for name, res, args in _EXTRA_SIGS:
+        if hasattr(L, name):
+            sig(name, res, *args)
+
+
+_EXTRA_SIGS = []
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().mpx_status_string(status)
+        raise MpxError(f"{what} failed: {msg.decode() if msg else status}")
+
+
+def prec_of(p) -> int:
+    if isinstance(p, str):
+        return PRECS[p.lower()]
+    if p not in _K:
+        raise ValueError(f"unknown precision {p!r}")
+    return int(p)
+
+
+def ncomp(p) -> int:
+    return _K[prec_of(p)]
+
+
+def dtype_of(p):
+    return torch.float32 if prec_of(p) == FF else torch.float64
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _planes(t: torch.Tensor, p, nd: int, name: str):
+    """Check a (K, ...) component-plane tensor; return (plane stride, ld)."""
+    K = ncomp(p)
+    if t.dim() != nd + 1 or t.shape[0] != K:
+        raise ValueError(f"{name}: expected shape (K={K}, ...) with {nd} trailing dims, got {tuple(t.shape)}")
+    if t.dtype != dtype_of(p):
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype_of(p)}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
+    if nd == 1:
+        if t.shape[1] > 1 and t.stride(1) != 1:
+            raise ValueError(f"{name}: components must be contiguous")
+        return t.stride(0), 0
+    if t.shape[2] > 1 and t.stride(2) != 1:
+        raise ValueError(f"{name}: rows must be contiguous")
+    return t.stride(0), t.stride(1)
+
+
+def workspace(op: int, p, m: int, n: int = 0, k: int = 0, extra: int = 0) -> torch.Tensor:
+    nbytes = int(lib().mpx_workspace_size(op, prec_of(p), m, n, k, extra))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+
+
+# ------------------------------------------------------------ elementwise ----
+
+def _ew(fn, p, x, y, out):
+    p = prec_of(p)
+    psx, _ = _planes(x, p, 1, "x")
+    psy, _ = _planes(y, p, 1, "y")
+    n = x.shape[1]
+    if y.shape[1] != n:
+        raise ValueError("x and y lengths differ")
+    if out is None:
+        out = torch.empty_like(x)
+    psz, _ = _planes(out, p, 1, "out")
+    _check(fn(p, n, _ptr(x), psx, _ptr(y), psy, _ptr(out), psz, _stream()), fn.__name__)
+    return out
+
+
+def add(p, x, y, out=None):
+    """Elementwise BF addition of two (K, n) tensors."""
+    return _ew(lib().mpx_add, p, x, y, out)
+
+
+def mul(p, x, y, out=None):
+    """Elementwise BF multiplication of two (K, n) tensors."""
+    return _ew(lib().mpx_mul, p, x, y, out)
+
+
+def axpy(p, alpha, x, y):
+    """y := alpha * x + y in place; alpha is a sequence of K host floats."""
+    p = prec_of(p)
+    psx, _ = _planes(x, p, 1, "x")
+    psy, _ = _planes(y, p, 1, "y")
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y lengths differ")
+    K = ncomp(p)
+    ctype = C.c_float if p == FF else C.c_double
+    a = (ctype * K)(*[float(v) for v in alpha])
+    _check(lib().mpx_axpy(p, x.shape[1], C.cast(a, C.c_void_p), _ptr(x), psx, _ptr(y), psy,
+                          _stream()), "mpx_axpy")
+    return y
+
+
+def dot(p, x, y, out=None, ws=None):
+    """K-component dot product of two (K, n) tensors -> (K,) tensor."""
+    p = prec_of(p)
+    psx, _ = _planes(x, p, 1, "x")
+    psy, _ = _planes(y, p, 1, "y")
+    n = x.shape[1]
+    if y.shape[1] != n:
+        raise ValueError("x and y lengths differ")
+    if out is None:
+        out = torch.empty(ncomp(p), dtype=dtype_of(p), device=x.device)
+    if ws is None:
+        ws = workspace(OP_DOT, p, n)
+    _check(lib().mpx_dot(p, n, _ptr(x), psx, _ptr(y), psy, _ptr(out), _ptr(ws), ws.numel(),
+                         _stream()), "mpx_dot")
+    return out
+
+
+def gemv(p, A, x, trans=False, out=None, ws=None):
+    """op(A) x for a (K, m, n) matrix A."""
+    p = prec_of(p)
+    psA, lda = _planes(A, p, 2, "A")
+    psx, _ = _planes(x, p, 1, "x")
+    m, n = A.shape[1], A.shape[2]
+    if x.shape[1] != (m if trans else n):
+        raise ValueError("x length does not match op(A)")
+    rows = n if trans else m
+    if out is None:
+        out = torch.empty((ncomp(p), rows), dtype=dtype_of(p), device=A.device)
+    psy, _ = _planes(out, p, 1, "out")
+    if ws is None:
+        ws = workspace(OP_GEMV, p, m, n, int(trans))
+    _check(lib().mpx_gemv(p, int(trans), m, n, _ptr(A), max(lda, n), psA, _ptr(x), psx,
+                          _ptr(out), psy, _ptr(ws), ws.numel(), _stream()), "mpx_gemv")
+    return out
+
+
+def _gemm_shapes(A, B, tA, tB):
+    m = A.shape[2] if tA else A.shape[1]
+    k = A.shape[1] if tA else A.shape[2]
+    n = B.shape[1] if tB else B.shape[2]
+    kb = B.shape[2] if tB else B.shape[1]
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    return m, n, k
+
+
+def gemm(p, A, B, transA=False, transB=False, out=None, variant=None):
+    """C = op(A) op(B) for (K, ., .) matrices; variant forces a kernel tiling."""
+    p = prec_of(p)
+    psA, lda = _planes(A, p, 2, "A")
+    psB, ldb = _planes(B, p, 2, "B")
+    m, n, k = _gemm_shapes(A, B, transA, transB)
+    if out is None:
+        out = torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=A.device)
+    psC, ldc = _planes(out, p, 2, "out")
+    lda = max(lda, A.shape[2]); ldb = max(ldb, B.shape[2]); ldc = max(ldc, n)
+    args = (int(transA), int(transB), m, n, k, _ptr(A), lda, psA, _ptr(B), ldb, psB,
+            _ptr(out), ldc, psC, _stream())
+    if variant is None:
+        _check(lib().mpx_gemm(p, *args), "mpx_gemm")
+    else:
+        _check(lib().mpx_gemm_variant(p, int(variant), *args), "mpx_gemm_variant")
+    return out
+
+
+def gemm_variants(p):
+    p = prec_of(p)
+    return [lib().mpx_gemm_variant_name(p, i).decode() for i in range(lib().mpx_gemm_variant_count(p))]
+
+
+def gemm_autotune(p, A, B, out, transA=False, transB=False, reps=3):
+    """Time every GEMM tiling on these buffers, remember the fastest for this
+    shape bucket; returns (variant index, ms)."""
+    p = prec_of(p)
+    psA, lda = _planes(A, p, 2, "A")
+    psB, ldb = _planes(B, p, 2, "B")
+    psC, ldc = _planes(out, p, 2, "out")
+    m, n, k = _gemm_shapes(A, B, transA, transB)
+    best = C.c_float()
+    r = lib().mpx_gemm_autotune(p, int(transA), int(transB), m, n, k, _ptr(A), max(lda, A.shape[2]),
+                                psA, _ptr(B), max(ldb, B.shape[2]), psB, _ptr(out), max(ldc, n),
+                                psC, reps, C.byref(best), _stream())
+    if r < 0:
+        _check(r, "mpx_gemm_autotune")
+    return r, best.value

@@ -1,0 +1,77 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/mpx.h, and rejects bad arguments before any launch (no
+GPU needed: argument errors return before the first HIP call)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2603_14926_amd import mpx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = set()
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(mpx_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mpx.lib()
+    names = _declared()
+    assert len(names) >= 10
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    L = mpx.lib()
+    assert L.mpx_version() >= 100
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.mpx_status_string(s)
+
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def test_bad_precision_rejected():
+    L = mpx.lib()
+    assert L.mpx_add(7, 10, FAKE, 10, FAKE, 10, FAKE, 10, None) == -2
+    assert L.mpx_gemm(5, 0, 0, 4, 4, 4, FAKE, 4, 16, FAKE, 4, 16, FAKE, 4, 16, None) == -2
+
+
+def test_bad_sizes_and_strides_rejected():
+    L = mpx.lib()
+    assert L.mpx_add(4, -1, FAKE, 10, FAKE, 10, FAKE, 10, None) == -1
+    assert L.mpx_add(4, 10, FAKE, 9, FAKE, 10, FAKE, 10, None) == -1      # plane stride < n
+    assert L.mpx_add(4, 10, None, 10, FAKE, 10, FAKE, 10, None) == -1     # null pointer
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 4, FAKE, 3, 16, FAKE, 4, 16, FAKE, 4, 16, None) == -1  # lda < k
+    assert L.mpx_gemm(4, 2, 0, 4, 4, 4, FAKE, 4, 16, FAKE, 4, 16, FAKE, 4, 16, None) == -1  # bad flag
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 4, FAKE, 4, 15, FAKE, 4, 16, FAKE, 4, 16, None) == -1  # psA small
+    assert L.mpx_gemv(4, 0, 4, 4, FAKE, 4, 16, FAKE, 4, FAKE, 3, None, 0, None) == -1       # psy < m
+    assert L.mpx_axpy(2, 4, None, FAKE, 4, FAKE, 4, None) == -1
+
+
+def test_workspace_checked():
+    L = mpx.lib()
+    n = 1 << 20
+    need = L.mpx_workspace_size(mpx.OP_DOT, 4, n, 0, 0, 0)
+    assert need > 0
+    assert L.mpx_dot(4, n, FAKE, n, FAKE, n, FAKE, FAKE, need - 1, None) == -4
+    assert L.mpx_dot(4, n, FAKE, n, FAKE, n, FAKE, None, 0, None) == -4
+    assert L.mpx_workspace_size(mpx.OP_DOT, 4, 100, 0, 0, 0) == 0   # small dot: one block
+    assert L.mpx_workspace_size(99, 4, 100, 0, 0, 0) == 0
+
+
+def test_empty_problems_are_noops():
+    L = mpx.lib()
+    assert L.mpx_add(4, 0, None, 0, None, 0, None, 0, None) == 0
+    assert L.mpx_gemm(4, 0, 0, 0, 5, 5, None, 5, 0, FAKE, 5, 25, None, 5, 0, None) == 0

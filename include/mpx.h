@@ -141,6 +141,91 @@ int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, int64_t n, in
                       float *best_ms, void *stream);
 void mpx_gemm_autotune_reset(void);
 
+/* ------------------------------------------------------------- Ozaki GEMM --
+ * C := A B for DD matrices (K = 2 planes, transposes not supported) by an
+ * Ozaki-style error-free split evaluated on the FP64 matrix cores.  The
+ * paper lists the Ozaki scheme among its GEMM schemes (Section 3.1) without
+ * defining it; the reading implemented:
+ *   e_i: max_l |A_il[0]| < 2^{e_i} (0 for a zero row); f_j likewise for the
+ *        columns of B;
+ *   slices: for p = 1..slices, m_p = rint(r1 * 2^{p*beta - e}),
+ *        (r1, r2) := TwoSum(r1 - m_p 2^{e - p*beta}, r2), from (hi, lo);
+ *   level sums over k-blocks of kblk: S_g = sum_{p+q=g} sum_l mA_p mB_q,
+ *        g = 2..slices+1, exact in binary64 (requires kblk * slices *
+ *        2^{2 beta} < 2^53, else MPX_EINVAL);
+ *   C_ij = DWBFAdd accumulation (k-blocks ascending, g ascending) of
+ *        (S_g 2^{e_i + f_j - g beta}, 0).
+ * slices in 1..12, kblk a positive multiple of 8.  The result is independent
+ * of the tiling (bit-reproducible).  ws: mpx_workspace_size(MPX_OP_OZAKI,
+ * MPX_DD, m, n, k, slices) bytes (the slice planes of A and B). */
+int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
+                      int64_t psA, const double *B, int64_t ldb, int64_t psB, double *C,
+                      int64_t ldc, int64_t psC, int slices, int beta, int64_t kblk, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ polynomials --
+ * Real Horner evaluation (Section 4.1): y_b = p_b(x_b) = sum_i a_{b,i} x_b^i
+ * for b < batch, all of degree deg >= 0.  Coefficient a_{b,i} (ascending
+ * powers) is column b*(deg+1) + i of the K coefficient planes (psc >=
+ * batch*(deg+1)); x, y are (K, batch) planes.  Per polynomial:
+ * h = a_deg; h := h*x + a_i for i = deg-1 .. 0.  DD / TD / QD only. */
+int mpx_polyval(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
+                const void *x, int64_t psx, void *y, int64_t psy, void *stream);
+
+/* Reverse mode of mpx_polyval for L = sum_b gy_b p_b(x_b):
+ *   gcoef_{b,i} = gy_b x_b^i  (t_0 = gy_b, t_{i+1} = t_i * x_b: the adjoint of
+ *                               the Horner recurrence), same layout as coef;
+ *   gx_b        = gy_b p_b'(x_b) (derivative recurrence d := d*x + h before
+ *                               each h := h*x + a_i, d = 0 initially).
+ * gcoef and gx are nullable (skipped when NULL). */
+int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
+                         const void *x, int64_t psx, const void *gy, int64_t psg, void *gcoef,
+                         int64_t psgc, void *gx, int64_t psgx, void *stream);
+
+/* Batched Durand-Kerner (Weierstrass) root finder, Section 4.2:
+ *   z_i <- z_i - q(z_i) / prod_{j != i} (z_i - z_j),  q = p / a_n  (monic),
+ * all new roots of a sweep from the previous iterate (Jacobi), `iters` sweeps,
+ * no early exit, complex K-component arithmetic (4M multiplication, division
+ * as x conj(y) / |y|^2 with Newton's reciprocal).  Optional Aberth start
+ * (MPX_DK_INIT): centre -c_{n-1}/n, radius r = max_i |n_nz c_i|^(1/(n-i)),
+ * angles 2(i-1)pi/n + 3/(2n), evaluated in binary64 (device libm) from the
+ * leading components of c_i = a_i/a_n; lower components start at zero.
+ * Horner values and the root-difference product are carried with exact
+ * power-of-two rescaling (no binary64 overflow at high degree).
+ *
+ * Layout: polynomial b has degree[b] >= 1; its coefficients a_0..a_n are
+ * columns coef_off[b] .. coef_off[b] + n of the K planes of coef_re and
+ * coef_im, where coef_off = prefix sums of (degree + 1); its roots are columns
+ * root_off[b] .. root_off[b] + n - 1 of roots_re / roots_im (prefix sums of
+ * degree).  roots_* hold the start values on entry (unless MPX_DK_INIT) and
+ * the iterate on return; passing them back resumes the iteration exactly.
+ * status[b] (nullable) = 0 if all roots of b are finite, 1 otherwise (e.g.
+ * coincident start values).
+ *
+ * A plan is created outside graph capture; it allocates its device schedule
+ * (polynomials in descending-degree order for load balance) and working
+ * buffers (monic coefficients, second iterate) and frees them in
+ * mpx_plan_destroy.  With MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots
+ * captures its launches into a HIP graph on first use and replays it while
+ * buffers and stream stay the same.  One persistent launch processes the
+ * whole batch.  Calls on one plan must not overlap. */
+typedef struct mpx_plan_s *mpx_plan;
+enum { MPX_DK_INIT = 1, MPX_DK_GRAPH = 2 };
+int mpx_polyroots_plan(mpx_plan *out, int prec, int64_t batch, const int32_t *degree_host,
+                       int iters, uint32_t flags);
+int mpx_polyroots(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
+                  void *roots_re, void *roots_im, int64_t psr, int32_t *status, void *stream);
+int mpx_plan_destroy(mpx_plan plan);
+/* Launch-shape variants (roots per lane, resident waves per CU); results do
+ * not depend on the variant.  The autotuner runs each for iters_probe sweeps
+ * on a private copy of the given start roots, keeps the fastest in the plan
+ * and returns its index (or a negative status).  Synchronises; allocates. */
+int mpx_polyroots_variant_count(void);
+int mpx_polyroots_set_variant(mpx_plan plan, int variant);
+int mpx_polyroots_autotune(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
+                           const void *roots_re, const void *roots_im, int64_t psr,
+                           int iters_probe, float *best_ms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

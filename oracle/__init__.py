@@ -369,14 +369,22 @@ def ozaki_split_cols(B, s, beta):
 
 
 def ozaki_entries(A, B, rows, cols, s, beta, kblk):
-    """Selected entries (2, cnt) of the Ozaki-split DD product."""
-    m, k = A.shape[1], A.shape[2]
-    n = B.shape[2]
-    e, sa = ozaki_split_rows(A, s, beta)
-    f, sb = ozaki_split_cols(B, s, beta)
+    """Selected entries (2, cnt) of the Ozaki-split DD product.  A row's split
+    depends only on that row (its own maximum), a column's only on that
+    column, so only the rows / columns asked for are split."""
+    A = _chk(A, 2); B = _chk(B, 2)
     rows = np.ascontiguousarray(rows, np.int64); cols = np.ascontiguousarray(cols, np.int64)
+    ur, ri = np.unique(rows, return_inverse=True)
+    uc, ci = np.unique(cols, return_inverse=True)
+    As = np.ascontiguousarray(A[:, ur, :])
+    Bs = np.ascontiguousarray(B[:, :, uc])
+    m, k = As.shape[1], As.shape[2]
+    n = Bs.shape[2]
+    e, sa = ozaki_split_rows(As, s, beta)
+    f, sb = ozaki_split_cols(Bs, s, beta)
+    r2 = np.ascontiguousarray(ri.astype(np.int64)); c2 = np.ascontiguousarray(ci.astype(np.int64))
     out = np.zeros((2, rows.size))
     lib().orc_ozaki_entries(_i64(m), _i64(n), _i64(k), _i32(s), _i32(beta), _i64(kblk),
-                            _p(e), _p(sa), _p(f), _p(sb), _i64(rows.size), _p(rows), _p(cols),
+                            _p(e), _p(sa), _p(f), _p(sb), _i64(rows.size), _p(r2), _p(c2),
                             _p(out))
     return out

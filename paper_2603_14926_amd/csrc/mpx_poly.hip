@@ -1,0 +1,686 @@
+// mpx_poly.hip -- polynomial kernels of libmpx on gfx950:
+//   * real Horner evaluation of a batch of polynomials and its reverse-mode
+//     derivative (Section 4.1 evaluates p_n(x) = sum a_i x^i by Horner);
+//   * the batched Durand-Kerner (Weierstrass) simultaneous iteration with
+//     the Aberth start (Section 4.2), as one persistent kernel.
+//
+// Durand-Kerner design.  A polynomial of degree n costs ~1672 n FP64 VALU
+// instructions per root per iteration in QD (Horner: n complex multiply-adds;
+// root-difference product: n-1 complex subtract-multiplies), i.e. O(n^2) per
+// iteration, all VALU.  One wave64 owns one polynomial at a time: lane l
+// updates roots l, l+64, ... (R of them interleaved for instruction-level
+// parallelism), reading the wave-uniform coefficient c_k and root z_j from
+// global memory (one cache line per load, broadcast to the 64 lanes).  The
+// iterate lives in two ping-pong buffers (the caller's roots and a plan-owned
+// copy); a workgroup barrier between iterations makes every update of
+// iterate t visible before iterate t+1 is read (Jacobi, as in the DK
+// equation: all new roots come from the previous iterate).  Waves take
+// polynomials from a longest-processing-time order (descending n^2) through
+// an atomic counter, so thousands of ragged degrees load-balance in one
+// launch.
+//
+// Overflow: Horner values grow like |z|^n (random degree-512 polynomials
+// start at |z| ~ 10^2), beyond binary64.  Values are therefore kept as
+// (mantissa, 2^E) with exact power-of-two rescaling after each step: the
+// Horner value is scaled down whenever its larger leading component reaches
+// 1 (the coefficient term is added as c_k 2^-E); the root-difference product
+// is rescaled to [0.5, 1) after every factor; the correction is
+// q/P * 2^(E - F).  Power-of-two scaling commutes with rounding, so this only
+// changes behaviour where the unscaled computation would overflow.
+//
+// Every per-root operation sequence equals the sequential definition (Horner
+// from the leading coefficient, j ascending in the product, Newton reciprocal
+// for the division), so results are bit-identical for every launch shape.
+#include "mp_arith.hpp"
+#include "mpx_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+namespace mpx {
+
+// ------------------------------------------------------- real Horner ----
+
+// y_b = p_b(x_b): h = a_deg; h := h * x + a_i (i = deg-1 .. 0).  One thread
+// per polynomial; coefficients for the next steps are loaded ahead of the
+// dependent multiply-add chain.
+template <int K>
+__global__ void __launch_bounds__(64)
+k_polyval(long long batch, long long deg, const double* __restrict__ coef, long long psc,
+          const double* __restrict__ x, long long psx, double* __restrict__ y, long long psy) {
+    using V = mpn<double, K>;
+    const long long b = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (b >= batch) return;
+    const long long off = b * (deg + 1);
+    const V xv = mp_load<double, K>(x, psx, b);
+    V h = mp_load<double, K>(coef, psc, off + deg);
+    long long i = deg - 1;
+    for (; i >= 3; i -= 4) {
+        const V a0 = mp_load<double, K>(coef, psc, off + i);
+        const V a1 = mp_load<double, K>(coef, psc, off + i - 1);
+        const V a2 = mp_load<double, K>(coef, psc, off + i - 2);
+        const V a3 = mp_load<double, K>(coef, psc, off + i - 3);
+        h = bf_add(bf_mul(h, xv), a0);
+        h = bf_add(bf_mul(h, xv), a1);
+        h = bf_add(bf_mul(h, xv), a2);
+        h = bf_add(bf_mul(h, xv), a3);
+    }
+    for (; i >= 0; --i) h = bf_add(bf_mul(h, xv), mp_load<double, K>(coef, psc, off + i));
+    mp_store<double, K>(y, psy, b, h);
+}
+
+// Gradients of L = sum_b g_b p_b(x_b):
+//   dL/da_{b,i} = t_i with t_0 = g_b, t_{i+1} = t_i * x_b   (adjoint of Horner)
+//   dL/dx_b     = g_b * d, d from  d := d * x + h  before  h := h * x + a_i
+// (d = 0, h = a_deg initially).  Either output may be null.
+template <int K>
+__global__ void __launch_bounds__(64)
+k_polyval_bwd(long long batch, long long deg, const double* __restrict__ coef, long long psc,
+              const double* __restrict__ x, long long psx, const double* __restrict__ g,
+              long long psg, double* __restrict__ gcoef, long long psgc,
+              double* __restrict__ gx, long long psgx) {
+    using V = mpn<double, K>;
+    const long long b = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (b >= batch) return;
+    const long long off = b * (deg + 1);
+    const V xv = mp_load<double, K>(x, psx, b);
+    const V gv = mp_load<double, K>(g, psg, b);
+    if (gcoef) {
+        V t = gv;
+        mp_store<double, K>(gcoef, psgc, off, t);
+        for (long long i = 1; i <= deg; ++i) {
+            t = bf_mul(t, xv);
+            mp_store<double, K>(gcoef, psgc, off + i, t);
+        }
+    }
+    if (gx) {
+        V h = mp_load<double, K>(coef, psc, off + deg);
+        V d = mp_zero<double, K>();
+        for (long long i = deg - 1; i >= 0; --i) {
+            const V a = mp_load<double, K>(coef, psc, off + i);
+            d = bf_add(bf_mul(d, xv), h);
+            h = bf_add(bf_mul(h, xv), a);
+        }
+        mp_store<double, K>(gx, psgx, b, bf_mul(gv, d));
+    }
+}
+
+// ------------------------------------------------- complex arithmetic ----
+
+template <int K>
+struct cplx {
+    mpn<double, K> re, im;
+};
+
+// (a+bi)(c+di): ac - bd, ad + bc (four BF products, two BF sums).
+template <int K>
+__device__ __forceinline__ cplx<K> c_mul(const cplx<K>& x, const cplx<K>& y) {
+    const auto ac = bf_mul(x.re, y.re);
+    const auto bd = bf_mul(x.im, y.im);
+    const auto ad = bf_mul(x.re, y.im);
+    const auto bc = bf_mul(x.im, y.re);
+    cplx<K> r;
+    r.re = bf_sub(ac, bd);
+    r.im = bf_add(ad, bc);
+    return r;
+}
+template <int K>
+__device__ __forceinline__ cplx<K> c_add(const cplx<K>& x, const cplx<K>& y) {
+    return {bf_add(x.re, y.re), bf_add(x.im, y.im)};
+}
+template <int K>
+__device__ __forceinline__ cplx<K> c_sub(const cplx<K>& x, const cplx<K>& y) {
+    return {bf_sub(x.re, y.re), bf_sub(x.im, y.im)};
+}
+
+// Newton's iteration for 1/d (division through Newton, Section 2): y0 is the
+// correctly rounded binary64 1/d_0; each step y := y + y (1 - d y) doubles
+// the correct bits (one step for DD, two for TD / QD).
+template <int K>
+__device__ __forceinline__ mpn<double, K> mp_recip(const mpn<double, K>& d) {
+    const auto one = mp_from<double, K>(1.0);
+    auto y = mp_from<double, K>(1.0 / d.c[0]);
+    constexpr int steps = K == 2 ? 1 : 2;
+#pragma unroll
+    for (int s = 0; s < steps; ++s) {
+        const auto e = bf_sub(one, bf_mul(d, y));
+        y = bf_add(y, bf_mul(y, e));
+    }
+    return y;
+}
+
+// x / y = (x conj y) (1 / |y|^2).
+template <int K>
+__device__ __forceinline__ cplx<K> c_div(const cplx<K>& x, const cplx<K>& y) {
+    const auto den = bf_add(bf_mul(y.re, y.re), bf_mul(y.im, y.im));
+    const auto inv = mp_recip<K>(den);
+    const auto nr = bf_add(bf_mul(x.re, y.re), bf_mul(x.im, y.im));
+    const auto ni = bf_sub(bf_mul(x.im, y.re), bf_mul(x.re, y.im));
+    return {bf_mul(nr, inv), bf_mul(ni, inv)};
+}
+
+// Component-wise select (a select on whole aggregates would go through memory).
+template <int K>
+__device__ __forceinline__ cplx<K> c_select(bool t, const cplx<K>& a, const cplx<K>& b) {
+    cplx<K> r;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        r.re.c[c] = t ? a.re.c[c] : b.re.c[c];
+        r.im.c[c] = t ? a.im.c[c] : b.im.c[c];
+    }
+    return r;
+}
+
+__device__ __forceinline__ int clamp_exp(long long e) {
+    return e > 100000 ? 100000 : (e < -100000 ? -100000 : (int)e);
+}
+
+template <int K>
+__device__ __forceinline__ cplx<K> c_ldexp(const cplx<K>& x, int e) {
+    cplx<K> r;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        r.re.c[c] = __builtin_amdgcn_ldexp(x.re.c[c], e);
+        r.im.c[c] = __builtin_amdgcn_ldexp(x.im.c[c], e);
+    }
+    return r;
+}
+
+// Rescale so the larger leading component lies in [0.5, 1) and add the
+// exponent to E; with down_only, only magnitudes >= 1 are rescaled.  Zero
+// and non-finite values are left alone.  Branch-free: the exponent used is
+// zero when no rescaling applies, and ldexp by zero is exact.
+template <int K, bool down_only>
+__device__ __forceinline__ void c_rescale(cplx<K>& z, long long& E) {
+    const double m = fmax(fabs(z.re.c[0]), fabs(z.im.c[0]));
+    const int e = __builtin_amdgcn_frexp_exp(m);  // m = f 2^e, 0.5 <= f < 1
+    const bool apply = (m != 0.0) && isfinite(m) && (!down_only || e >= 1);
+    const int s = apply ? e : 0;
+    z = c_ldexp<K>(z, -s);
+    E += s;
+}
+
+template <int K>
+__device__ __forceinline__ cplx<K> c_load(const double* __restrict__ re,
+                                          const double* __restrict__ im, long long ps,
+                                          long long idx) {
+    return {mp_load<double, K>(re, ps, idx), mp_load<double, K>(im, ps, idx)};
+}
+template <int K>
+__device__ __forceinline__ void c_store(double* __restrict__ re, double* __restrict__ im,
+                                        long long ps, long long idx, const cplx<K>& v) {
+    mp_store<double, K>(re, ps, idx, v.re);
+    mp_store<double, K>(im, ps, idx, v.im);
+}
+
+// ------------------------------------------------------ Durand-Kerner ----
+
+struct DkPlanDev {
+    const int* order;          // polynomial indices, LPT order
+    const int* degree;         // per polynomial
+    const long long* coef_off; // first coefficient column of polynomial b
+    const long long* root_off; // first root column of polynomial b
+    double* mre;               // monic coefficient planes (same columns as coefficients)
+    double* mim;
+    double* zre;               // second iterate buffer (same columns as roots)
+    double* zim;
+    int* counter;              // work counter
+    long long psm, psz;        // plane strides of the plan buffers
+};
+
+__global__ void k_reset_counter(int* c) { *c = 0; }
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Prologue, one wave per polynomial: monic coefficients c_i = a_i / a_n and,
+// with init, the Aberth start values (binary64, leading components).
+template <int K>
+__global__ void __launch_bounds__(64)
+k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
+              const double* __restrict__ aim, long long psc, double* rre, double* rim,
+              long long psr, int init) {
+    using C = cplx<K>;
+    const int lane = threadIdx.x;
+    for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+        const int n = P.degree[b];
+        const long long co = P.coef_off[b], ro = P.root_off[b];
+        const C an = c_load<K>(are, aim, psc, co + n);
+        for (int i = lane; i < n; i += 64)
+            c_store<K>(P.mre, P.mim, P.psm, co + i, c_div<K>(c_load<K>(are, aim, psc, co + i), an));
+        if (!init) continue;
+        __syncthreads();
+        int nnz = 0;
+        for (int i = lane; i < n; i += 64)
+            nnz += (P.mre[co + i] != 0.0 || P.mim[co + i] != 0.0) ? 1 : 0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nnz += __shfl_xor(nnz, off, 64);
+        double r = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double mag = hypot(P.mre[co + i], P.mim[co + i]) * (double)nnz;
+            const double t = pow(mag, 1.0 / (double)(n - i));
+            if (t > r) r = t;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+        const double cre = -P.mre[co + n - 1] / (double)n;
+        const double cim = -P.mim[co + n - 1] / (double)n;
+        for (int i = lane; i < n; i += 64) {
+            const double th = 2.0 * (double)i * kPi / (double)n + 3.0 / (2.0 * (double)n);
+            C z;
+            z.re = mp_from<double, K>(cre + r * cos(th));
+            z.im = mp_from<double, K>(cim + r * sin(th));
+            c_store<K>(rre, rim, psr, ro + i, z);
+        }
+        __syncthreads();
+    }
+}
+
+// Persistent iteration kernel: waves pull polynomials in LPT order.
+template <int K, int R>
+__global__ void __launch_bounds__(64)
+k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr, int* status,
+                int iters) {
+    using C = cplx<K>;
+    const int lane = threadIdx.x;
+    for (;;) {
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(P.counter, 1);
+        slot = __shfl(slot, 0, 64);
+        if (slot >= batch) break;  // wave-uniform exit
+        const int b = P.order[slot];
+        const int n = P.degree[b];
+        const long long co = P.coef_off[b], ro = P.root_off[b];
+
+        const double* mre = P.mre + co;
+        const double* mim = P.mim + co;
+        for (int it = 0; it < iters; ++it) {
+            const bool from_user = (it & 1) == 0;
+            const double* sre = from_user ? rre : P.zre;
+            const double* sim = from_user ? rim : P.zim;
+            double* dre = from_user ? P.zre : rre;
+            double* dim = from_user ? P.zim : rim;
+            const long long pss = from_user ? psr : P.psz;
+            const long long psd = from_user ? P.psz : psr;
+            for (int base = lane; base < n; base += 64 * R) {
+                int idx[R];
+                C z[R], h[R];
+                long long E[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    idx[r] = base + 64 * r;
+                    const int ic = idx[r] < n ? idx[r] : n - 1;
+                    z[r] = c_load<K>(sre, sim, pss, ro + ic);
+                    h[r].re = mp_from<double, K>(1.0);
+                    h[r].im = mp_zero<double, K>();
+                    E[r] = 0;
+                }
+                // q(z) by Horner on the monic coefficients
+#pragma nounroll
+                for (int k = n - 1; k >= 0; --k) {
+                    const C ck = c_load<K>(mre, mim, P.psm, k);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        h[r] = c_add<K>(c_mul<K>(h[r], z[r]), c_ldexp<K>(ck, clamp_exp(-E[r])));
+                        c_rescale<K, true>(h[r], E[r]);
+                    }
+                }
+                // prod_{j != i} (z_i - z_j), j ascending
+                C Pp[R];
+                long long F[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    Pp[r].re = mp_from<double, K>(1.0);
+                    Pp[r].im = mp_zero<double, K>();
+                    F[r] = 0;
+                }
+#pragma nounroll
+                for (int j = 0; j < n; ++j) {
+                    const C zj = c_load<K>(sre, sim, pss, ro + j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        C t = c_mul<K>(Pp[r], c_sub<K>(z[r], zj));
+                        long long Ft = F[r];
+                        c_rescale<K, false>(t, Ft);
+                        const bool take = j != idx[r];
+                        Pp[r] = c_select<K>(take, t, Pp[r]);
+                        F[r] = take ? Ft : F[r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C w = c_ldexp<K>(c_div<K>(h[r], Pp[r]), clamp_exp(E[r] - F[r]));
+                    if (idx[r] < n) c_store<K>(dre, dim, psd, ro + idx[r], c_sub<K>(z[r], w));
+                }
+            }
+            __syncthreads();  // iterate t complete before t+1 reads it
+        }
+        if (iters & 1) {  // result is in the plan buffer: copy back to the caller's
+            for (int i = lane; i < n; i += 64)
+                c_store<K>(rre, rim, psr, ro + i, c_load<K>(P.zre, P.zim, P.psz, ro + i));
+            __syncthreads();
+        }
+        if (status) {
+            int bad = 0;
+            for (int i = lane; i < n; i += 64) {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    bad |= !isfinite(rre[c * psr + ro + i]) || !isfinite(rim[c * psr + ro + i]);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+            if (lane == 0) status[b] = bad;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- plan ----
+
+struct DkVariant {
+    int r;          // roots per lane processed together
+    int waves_cu;   // resident waves per CU targeted by the grid size
+};
+static const DkVariant kDkVariants[] = {{1, 8}, {2, 8}, {1, 16}, {2, 12}};
+constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
+
+}  // namespace mpx
+
+// Opaque plan (declared in mpx.h as struct mpx_plan_s).
+struct mpx_plan_s {
+    int prec = 0, K = 0, batch = 0, iters = 0;
+    unsigned flags = 0;
+    int variant = 1;
+    long long total_coef = 0, total_roots = 0;
+    int cus = 256;
+    void* dev = nullptr;            // one allocation: schedule + offsets + buffers
+    mpx::DkPlanDev d{};
+    // graph cache
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* g_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    long long g_ps[2] = {0, 0};
+    hipStream_t g_stream = nullptr;
+    int g_variant = -1;
+};
+
+namespace mpx {
+
+template <int K, int R>
+static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long long psc, void* rre,
+                       void* rim, long long psr, int* status, int waves_cu, hipStream_t s) {
+    k_reset_counter<<<1, 1, 0, s>>>(p->d.counter);
+    int st = launch_status();
+    if (st) return st;
+    long long grid = (long long)p->cus * waves_cu;
+    if (grid > p->batch) grid = p->batch;
+    if (grid < 1) grid = 1;
+    k_dk_prologue<K><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (const double*)are,
+                                                  (const double*)aim, psc, (double*)rre,
+                                                  (double*)rim, psr,
+                                                  (p->flags & MPX_DK_INIT) ? 1 : 0);
+    if ((st = launch_status())) return st;
+    k_durand_kerner<K, R><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
+                                                        (double*)rim, psr, status, p->iters);
+    return launch_status();
+}
+
+static int launch_dk(mpx_plan_s* p, int variant, const void* are, const void* aim, long long psc,
+                     void* rre, void* rim, long long psr, int* status, hipStream_t s) {
+    const DkVariant v = kDkVariants[variant];
+#define MPX_DK_CASE(KK)                                                                        \
+    if (p->K == KK) {                                                                          \
+        if (v.r == 1) return launch_dk_t<KK, 1>(p, are, aim, psc, rre, rim, psr, status,      \
+                                                v.waves_cu, s);                                \
+        return launch_dk_t<KK, 2>(p, are, aim, psc, rre, rim, psr, status, v.waves_cu, s);    \
+    }
+    MPX_DK_CASE(2)
+    MPX_DK_CASE(3)
+    MPX_DK_CASE(4)
+#undef MPX_DK_CASE
+    return MPX_EPREC;
+}
+
+}  // namespace mpx
+
+using namespace mpx;
+
+// ---------------------------------------------------------------- C ABI ----
+
+static int polyval_check(int prec, int64_t batch, int64_t deg, const void* coef, int64_t psc,
+                         const void* x, int64_t psx) {
+    if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
+    if (batch < 0 || deg < 0) return MPX_EINVAL;
+    if (batch == 0) return MPX_OK;
+    if (coef == nullptr || psc < batch * (deg + 1) || x == nullptr || psx < batch) return MPX_EINVAL;
+    return MPX_OK;
+}
+
+extern "C" int mpx_polyval(int prec, int64_t batch, int64_t deg, const void* coef, int64_t psc,
+                           const void* x, int64_t psx, void* y, int64_t psy, void* stream) {
+    int st = polyval_check(prec, batch, deg, coef, psc, x, psx);
+    if (st) return st;
+    if (batch == 0) return MPX_OK;
+    if (y == nullptr || psy < batch) return MPX_EINVAL;
+    const unsigned blocks = (unsigned)ceil_div(batch, 64);
+    hipStream_t s = as_stream(stream);
+    switch (prec) {
+        case MPX_DD: k_polyval<2><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
+        case MPX_TD: k_polyval<3><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
+        default: k_polyval<4><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
+    }
+    return launch_status();
+}
+
+extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void* coef,
+                                    int64_t psc, const void* x, int64_t psx, const void* gy,
+                                    int64_t psg, void* gcoef, int64_t psgc, void* gx,
+                                    int64_t psgx, void* stream) {
+    int st = polyval_check(prec, batch, deg, coef, psc, x, psx);
+    if (st) return st;
+    if (batch == 0) return MPX_OK;
+    if (gy == nullptr || psg < batch) return MPX_EINVAL;
+    if (gcoef && psgc < batch * (deg + 1)) return MPX_EINVAL;
+    if (gx && psgx < batch) return MPX_EINVAL;
+    if (!gcoef && !gx) return MPX_OK;
+    const unsigned blocks = (unsigned)ceil_div(batch, 64);
+    hipStream_t s = as_stream(stream);
+#define MPX_PB(KK)                                                                             \
+    k_polyval_bwd<KK><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc,              \
+                                            (const double*)x, psx, (const double*)gy, psg,     \
+                                            (double*)gcoef, psgc, (double*)gx, psgx)
+    switch (prec) {
+        case MPX_DD: MPX_PB(2); break;
+        case MPX_TD: MPX_PB(3); break;
+        default: MPX_PB(4); break;
+    }
+#undef MPX_PB
+    return launch_status();
+}
+
+extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
+                                  const int32_t* degree_host, int iters, uint32_t flags) {
+    if (out == nullptr) return MPX_EINVAL;
+    *out = nullptr;
+    if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
+    if (batch < 0 || batch > INT32_MAX || (degree_host == nullptr && batch > 0) || iters < 0)
+        return MPX_EINVAL;
+    if (flags & ~(uint32_t)(MPX_DK_INIT | MPX_DK_GRAPH)) return MPX_EINVAL;
+    std::vector<int> deg(batch), order(batch);
+    std::vector<long long> coff(batch + 1), roff(batch + 1);
+    coff[0] = roff[0] = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        if (degree_host[b] < 1) return MPX_EINVAL;
+        deg[b] = degree_host[b];
+        coff[b + 1] = coff[b] + deg[b] + 1;
+        roff[b + 1] = roff[b] + deg[b];
+        order[b] = (int)b;
+    }
+    // longest-processing-time order: descending n^2 (ties: index order)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+
+    auto* p = new (std::nothrow) mpx_plan_s();
+    if (!p) return MPX_EINVAL;
+    p->prec = prec;
+    p->K = prec_k(prec);
+    p->batch = (int)batch;
+    p->iters = iters;
+    p->flags = flags;
+    p->total_coef = coff[batch];
+    p->total_roots = roff[batch];
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        p->cus = prop.multiProcessorCount;
+
+    const size_t n_i = (size_t)batch, K = (size_t)p->K;
+    const size_t sz_order = n_i * sizeof(int), sz_deg = n_i * sizeof(int);
+    const size_t sz_off = (n_i + 1) * sizeof(long long);
+    const size_t sz_m = 2 * K * (size_t)std::max<long long>(p->total_coef, 1) * sizeof(double);
+    const size_t sz_z = 2 * K * (size_t)std::max<long long>(p->total_roots, 1) * sizeof(double);
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t total = al(sz_order) + al(sz_deg) + 2 * al(sz_off) + al(sz_m) + al(sz_z) + 256;
+    if (hipMalloc(&p->dev, total) != hipSuccess) { delete p; return MPX_EDEVICE; }
+    char* c = (char*)p->dev;
+    auto take = [&](size_t v) { char* r = c; c += al(v); return r; };
+    int* d_order = (int*)take(sz_order);
+    int* d_deg = (int*)take(sz_deg);
+    long long* d_coff = (long long*)take(sz_off);
+    long long* d_roff = (long long*)take(sz_off);
+    double* d_m = (double*)take(sz_m);
+    double* d_z = (double*)take(sz_z);
+    int* d_cnt = (int*)take(256);
+    hipError_t e = hipSuccess;
+    if (batch > 0) {
+        e = hipMemcpy(d_order, order.data(), sz_order, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_deg, deg.data(), sz_deg, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(d_coff, coff.data(), sz_off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_roff, roff.data(), sz_off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { hipFree(p->dev); delete p; return MPX_EDEVICE; }
+    const long long psm = std::max<long long>(p->total_coef, 1);
+    const long long psz = std::max<long long>(p->total_roots, 1);
+    p->d = DkPlanDev{d_order, d_deg, d_coff, d_roff, d_m, d_m + K * psm, d_z, d_z + K * psz,
+                     d_cnt, psm, psz};
+    *out = p;
+    return MPX_OK;
+}
+
+extern "C" int mpx_plan_destroy(mpx_plan p) {
+    if (!p) return MPX_OK;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->dev) hipFree(p->dev);
+    delete p;
+    return MPX_OK;
+}
+
+static int roots_check(mpx_plan p, const void* cre, const void* cim, int64_t psc, void* rre,
+                       void* rim, int64_t psr) {
+    if (!p) return MPX_EINVAL;
+    if (p->batch == 0) return MPX_OK;
+    if (!cre || !cim || !rre || !rim) return MPX_EINVAL;
+    if (psc < p->total_coef || psr < p->total_roots) return MPX_EINVAL;
+    return MPX_OK;
+}
+
+extern "C" int mpx_polyroots(mpx_plan p, const void* coef_re, const void* coef_im, int64_t psc,
+                             void* roots_re, void* roots_im, int64_t psr, int32_t* status,
+                             void* stream) {
+    int st = roots_check(p, coef_re, coef_im, psc, roots_re, roots_im, psr);
+    if (st) return st;
+    if (p->batch == 0) return MPX_OK;
+    hipStream_t s = as_stream(stream);
+    if (!(p->flags & MPX_DK_GRAPH) || s == nullptr)
+        return launch_dk(p, p->variant, coef_re, coef_im, psc, roots_re, roots_im, psr, status, s);
+    // Graph path: capture the launch sequence once per (buffers, stream, variant), replay after.
+    const void* key[6] = {coef_re, coef_im, roots_re, roots_im, status, nullptr};
+    bool same = p->exec && p->g_stream == s && p->g_variant == p->variant && p->g_ps[0] == psc &&
+                p->g_ps[1] == psr;
+    for (int i = 0; i < 6 && same; ++i) same = key[i] == p->g_key[i];
+    if (!same) {
+        if (p->exec) { hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPX_EDEVICE;
+        st = launch_dk(p, p->variant, coef_re, coef_im, psc, roots_re, roots_im, psr, status, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st || e != hipSuccess) { if (g) hipGraphDestroy(g); return st ? st : MPX_EDEVICE; }
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return MPX_EDEVICE;
+        }
+        p->graph = g;
+        for (int i = 0; i < 6; ++i) p->g_key[i] = key[i];
+        p->g_stream = s;
+        p->g_variant = p->variant;
+        p->g_ps[0] = psc;
+        p->g_ps[1] = psr;
+    }
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? MPX_OK : MPX_EDEVICE;
+}
+
+extern "C" int mpx_polyroots_variant_count(void) { return kDkVariantCount; }
+
+extern "C" int mpx_polyroots_set_variant(mpx_plan p, int variant) {
+    if (!p || variant < 0 || variant >= kDkVariantCount) return MPX_EINVAL;
+    p->variant = variant;
+    return MPX_OK;
+}
+
+// Autotuner: run each launch variant for `iters_probe` iterations on a copy
+// of the given start roots (the caller's roots are not modified), time it
+// with HIP events, and keep the fastest in the plan.  Synchronises `stream`.
+extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const void* coef_im,
+                                      int64_t psc, const void* roots_re, const void* roots_im,
+                                      int64_t psr, int iters_probe, float* best_ms,
+                                      void* stream) {
+    int st = roots_check(p, coef_re, coef_im, psc, (void*)roots_re, (void*)roots_im, psr);
+    if (st) return st;
+    if (p->batch == 0 || iters_probe < 1) return MPX_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const size_t plane = (size_t)p->total_roots * sizeof(double);
+    double* tmp = nullptr;
+    if (hipMalloc(&tmp, 2 * p->K * plane) != hipSuccess) return MPX_EDEVICE;
+    double* tre = tmp;
+    double* tim = tmp + (size_t)p->K * p->total_roots;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const int saved_iters = p->iters;
+    const unsigned saved_flags = p->flags;
+    p->iters = iters_probe;
+    p->flags &= ~(unsigned)MPX_DK_INIT;
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < kDkVariantCount && !st; ++v) {
+        for (int c = 0; c < p->K && !st; ++c) {
+            if (hipMemcpyAsync(tre + (size_t)c * p->total_roots, (const double*)roots_re + (size_t)c * psr,
+                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(tim + (size_t)c * p->total_roots, (const double*)roots_im + (size_t)c * psr,
+                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                st = MPX_EDEVICE;
+        }
+        if (st) break;
+        hipEventRecord(e0, s);
+        st = launch_dk(p, v, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);
+        hipEventRecord(e1, s);
+        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+    }
+    p->iters = saved_iters;
+    p->flags = saved_flags;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(tmp);
+    if (st) return st;
+    p->variant = best;
+    if (best_ms) *best_ms = best_t;
+    return best;
+}

@@ -69,6 +69,15 @@ def _declare(L):
     sig("mpx_gemm_autotune", _i, _i, _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i,
         C.POINTER(C.c_float), _v)
     sig("mpx_gemm_autotune_reset", None)
+    sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
+    sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
+    sig("mpx_polyroots", _i, _v, _v, _v, _l, _v, _v, _l, _v, _v)
+    sig("mpx_plan_destroy", _i, _v)
+    sig("mpx_polyroots_variant_count", _i)
+    sig("mpx_polyroots_set_variant", _i, _v, _i)
+    sig("mpx_polyroots_autotune", _i, _v, _v, _v, _l, _v, _v, _l, _i, C.POINTER(C.c_float), _v)
     for name, res, args in _EXTRA_SIGS:
         if hasattr(L, name):
             sig(name, res, *args)
@@ -116,6 +125,8 @@ def _planes(t: torch.Tensor, p, nd: int, name: str):
         raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype_of(p)}")
     if not t.is_cuda:
         raise ValueError(f"{name}: must be a GPU tensor")
+    if t.numel() == 0:
+        return max(t.stride(0), 0), (t.shape[2] if nd == 2 else 0)
     if nd == 1:
         if t.shape[1] > 1 and t.stride(1) != 1:
             raise ValueError(f"{name}: components must be contiguous")
@@ -236,6 +247,22 @@ def gemm(p, A, B, transA=False, transB=False, out=None, variant=None):
     return out
 
 
+def gemm_ozaki_dd(A, B, slices, beta=20, kblk=256, out=None, ws=None):
+    """DD product by the Ozaki-style split on FP64 MFMA; A (2, m, k), B (2, k, n)."""
+    psA, lda = _planes(A, DD, 2, "A")
+    psB, ldb = _planes(B, DD, 2, "B")
+    m, n, k = _gemm_shapes(A, B, False, False)
+    if out is None:
+        out = torch.empty((2, m, n), dtype=torch.float64, device=A.device)
+    psC, ldc = _planes(out, DD, 2, "out")
+    if ws is None:
+        ws = workspace(OP_OZAKI, DD, m, n, k, slices)
+    _check(lib().mpx_gemm_ozaki_dd(m, n, k, _ptr(A), max(lda, k), psA, _ptr(B), max(ldb, n), psB,
+                                   _ptr(out), max(ldc, n), psC, int(slices), int(beta), int(kblk),
+                                   _ptr(ws), ws.numel(), _stream()), "mpx_gemm_ozaki_dd")
+    return out
+
+
 def gemm_variants(p):
     p = prec_of(p)
     return [lib().mpx_gemm_variant_name(p, i).decode() for i in range(lib().mpx_gemm_variant_count(p))]
@@ -256,3 +283,113 @@ def gemm_autotune(p, A, B, out, transA=False, transB=False, reps=3):
     if r < 0:
         _check(r, "mpx_gemm_autotune")
     return r, best.value
+
+
+# ------------------------------------------------------------ polynomials ----
+
+def polyval(p, coef, x, out=None):
+    """y_b = sum_i coef[:, b, i] x_b^i by Horner; coef (K, batch, deg+1), x (K, batch)."""
+    p = prec_of(p)
+    if p == FF:
+        raise ValueError("polyval supports DD / TD / QD")
+    K = ncomp(p)
+    if coef.dim() != 3 or coef.shape[0] != K:
+        raise ValueError("coef must be (K, batch, deg+1)")
+    coef = coef.contiguous()
+    psx, _ = _planes(x, p, 1, "x")
+    batch, d1 = coef.shape[1], coef.shape[2]
+    if x.shape[1] != batch:
+        raise ValueError("x must have one point per polynomial")
+    if out is None:
+        out = torch.empty((K, batch), dtype=torch.float64, device=coef.device)
+    psy, _ = _planes(out, p, 1, "out")
+    _check(lib().mpx_polyval(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(out),
+                             psy, _stream()), "mpx_polyval")
+    return out
+
+
+def polyval_backward(p, coef, x, gy, want_coef=True, want_x=True):
+    """(dL/dcoef, dL/dx) for L = sum_b gy_b p_b(x_b); entries None when not wanted."""
+    p = prec_of(p)
+    K = ncomp(p)
+    coef = coef.contiguous()
+    psx, _ = _planes(x, p, 1, "x")
+    psg, _ = _planes(gy, p, 1, "gy")
+    batch, d1 = coef.shape[1], coef.shape[2]
+    gc = torch.empty_like(coef) if want_coef else None
+    gx = torch.empty((K, batch), dtype=torch.float64, device=coef.device) if want_x else None
+    _check(lib().mpx_polyval_backward(
+        p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(gy), psg,
+        _ptr(gc) if gc is not None else None, gc.stride(0) if gc is not None else 0,
+        _ptr(gx) if gx is not None else None, gx.stride(0) if gx is not None else 0,
+        _stream()), "mpx_polyval_backward")
+    return gc, gx
+
+
+DK_INIT, DK_GRAPH = 1, 2
+
+
+class RootsPlan:
+    """Plan for the batched Durand-Kerner solver (owns its device buffers).
+
+    degrees: host sequence of polynomial degrees (>= 1).  Coefficient columns
+    are packed: polynomial b occupies columns coef_off[b] .. coef_off[b] +
+    deg[b] of (K, total_coef) planes; roots likewise with (K, total_roots)."""
+
+    def __init__(self, p, degrees, iters=200, init=True, graph=True):
+        import numpy as np
+        self.p = prec_of(p)
+        if self.p == FF:
+            raise ValueError("polyroots supports DD / TD / QD")
+        self.K = ncomp(self.p)
+        self.degrees = np.ascontiguousarray(degrees, dtype=np.int32)
+        self.total_coef = int((self.degrees.astype(np.int64) + 1).sum())
+        self.total_roots = int(self.degrees.astype(np.int64).sum())
+        flags = (DK_INIT if init else 0) | (DK_GRAPH if graph else 0)
+        h = C.c_void_p()
+        _check(lib().mpx_polyroots_plan(C.byref(h), self.p, self.degrees.size,
+                                        self.degrees.ctypes.data_as(C.c_void_p), int(iters), flags),
+               "mpx_polyroots_plan")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mpx_plan_destroy(h)
+            self._h = None
+
+    def _args(self, cre, cim, zre, zim):
+        for t, name, cols in ((cre, "coef_re", self.total_coef), (cim, "coef_im", self.total_coef),
+                              (zre, "roots_re", self.total_roots), (zim, "roots_im", self.total_roots)):
+            _planes(t, self.p, 1, name)
+            if t.shape[1] != cols:
+                raise ValueError(f"{name}: expected {cols} columns, got {t.shape[1]}")
+        if cre.stride(0) != cim.stride(0) or zre.stride(0) != zim.stride(0):
+            raise ValueError("real and imaginary planes must share a plane stride")
+
+    def run(self, coef_re, coef_im, roots_re, roots_im, status=None):
+        """Iterate in place on roots_re / roots_im; returns the status tensor."""
+        self._args(coef_re, coef_im, roots_re, roots_im)
+        if status is None:
+            status = torch.zeros(self.degrees.size, dtype=torch.int32, device=coef_re.device)
+        _check(lib().mpx_polyroots(self._h, _ptr(coef_re), _ptr(coef_im), coef_re.stride(0),
+                                   _ptr(roots_re), _ptr(roots_im), roots_re.stride(0),
+                                   _ptr(status), _stream()), "mpx_polyroots")
+        return status
+
+    def set_variant(self, v):
+        _check(lib().mpx_polyroots_set_variant(self._h, int(v)), "mpx_polyroots_set_variant")
+
+    def autotune(self, coef_re, coef_im, roots_re, roots_im, iters_probe=2):
+        self._args(coef_re, coef_im, roots_re, roots_im)
+        best = C.c_float()
+        r = lib().mpx_polyroots_autotune(self._h, _ptr(coef_re), _ptr(coef_im), coef_re.stride(0),
+                                         _ptr(roots_re), _ptr(roots_im), roots_re.stride(0),
+                                         int(iters_probe), C.byref(best), _stream())
+        if r < 0:
+            _check(r, "mpx_polyroots_autotune")
+        return r, best.value
+
+
+def polyroots_variant_count() -> int:
+    return int(lib().mpx_polyroots_variant_count())

@@ -1,0 +1,164 @@
+"""GPU parity of the polynomial kernels against the CPU oracle: real Horner
+and its backward (bit-exact), and the batched Durand-Kerner solver
+(bit-exact per iteration from identical start values; Aberth start values
+within binary64 rounding, since they use device libm)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2603_14926_amd import mpx, synth
+from tests.gpu_util import bits_equal, first_mismatch, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [("dd", 2), ("td", 3), ("qd", 4)]
+
+
+@pytest.mark.parametrize("p,K", PRECS)
+@pytest.mark.parametrize("batch,deg", [(1, 0), (5, 1), (70, 33), (130, 257), (1024, 1024)])
+def test_polyval_and_backward_bit_exact(p, K, batch, deg):
+    coef = synth.mp_array(K, (batch, deg + 1), 1 + deg, "U")
+    x = synth.mp_array(K, batch, 2 + deg, "U")
+    g = synth.mp_array(K, batch, 3 + deg, "U")
+    gcoef, gx, gg = to_gpu(coef), to_gpu(x), to_gpu(g)
+    y = to_np(mpx.polyval(p, gcoef, gx))
+    want = oracle.polyval(K, coef, x)
+    assert bits_equal(y, want), first_mismatch(y, want)
+    dc, dx = mpx.polyval_backward(p, gcoef, gx, gg)
+    wc, wx = oracle.polyval_backward(K, coef, x, g)
+    assert bits_equal(to_np(dc), wc), first_mismatch(to_np(dc), wc)
+    assert bits_equal(to_np(dx), wx)
+
+
+def _dk_inputs(K, degrees, seed):
+    degrees = np.asarray(degrees, np.int32)
+    total = int((degrees + 1).sum())
+    cre = synth.mp_array(K, total, seed, "N")
+    cim = synth.mp_array(K, total, seed + 1, "N")
+    return degrees, cre, cim
+
+
+RAGGED = [1, 2, 3, 17, 64, 65, 130, 5, 40]
+
+
+@pytest.mark.parametrize("p,K", PRECS)
+def test_dk_iterations_bit_exact_from_same_start(p, K):
+    deg, cre, cim = _dk_inputs(K, RAGGED, 10 + K)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, wst = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=6, init=False)
+    for v in range(mpx.polyroots_variant_count()):
+        plan = mpx.RootsPlan(p, deg, iters=6, init=False, graph=False)
+        plan.set_variant(v)
+        zr, zi = to_gpu(z0r), to_gpu(z0i)
+        st = plan.run(to_gpu(cre), to_gpu(cim), zr, zi)
+        assert bits_equal(to_np(zr), wr), (v, first_mismatch(to_np(zr), wr))
+        assert bits_equal(to_np(zi), wi), v
+        assert np.array_equal(to_np(st), wst)
+
+
+def test_dk_odd_and_even_iteration_counts_and_resume():
+    K = 4
+    deg, cre, cim = _dk_inputs(K, [7, 33, 2, 64], 20)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    gc_r, gc_i = to_gpu(cre), to_gpu(cim)
+    for iters in (0, 1, 2, 5):
+        wr, wi, _ = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=iters, init=False)
+        zr, zi = to_gpu(z0r), to_gpu(z0i)
+        mpx.RootsPlan("qd", deg, iters=iters, init=False, graph=False).run(gc_r, gc_i, zr, zi)
+        assert bits_equal(to_np(zr), wr) and bits_equal(to_np(zi), wi), iters
+    # 3 + 2 iterations == 5 iterations (resume from the current roots)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    mpx.RootsPlan("qd", deg, iters=3, init=False, graph=False).run(gc_r, gc_i, zr, zi)
+    mpx.RootsPlan("qd", deg, iters=2, init=False, graph=False).run(gc_r, gc_i, zr, zi)
+    wr, wi, _ = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=5, init=False)
+    assert bits_equal(to_np(zr), wr) and bits_equal(to_np(zi), wi)
+
+
+@pytest.mark.parametrize("p,K", PRECS)
+def test_dk_aberth_start_close_to_oracle(p, K):
+    deg, cre, cim = _dk_inputs(K, RAGGED, 30 + K)
+    wr, wi, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    zr = torch.zeros((K, int(deg.sum())), dtype=torch.float64, device="cuda")
+    zi = torch.zeros_like(zr)
+    mpx.RootsPlan(p, deg, iters=0, init=True, graph=False).run(to_gpu(cre), to_gpu(cim), zr, zi)
+    gr, gi = to_np(zr), to_np(zi)
+    scale = np.maximum(np.abs(wr[0]) + np.abs(wi[0]), 1e-300)
+    assert np.max((np.abs(gr[0] - wr[0]) + np.abs(gi[0] - wi[0])) / scale) < 1e-13
+    assert np.all(gr[1:] == 0) and np.all(gi[1:] == 0)
+
+
+def test_dk_graph_replay_matches_eager():
+    K = 4
+    deg, cre, cim = _dk_inputs(K, [16, 31, 48, 3, 9], 40)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, _ = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=4, init=False)
+    stream = torch.cuda.Stream()
+    plan = mpx.RootsPlan("qd", deg, iters=4, init=False, graph=True)
+    gc_r, gc_i = to_gpu(cre), to_gpu(cim)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    st = torch.zeros(deg.size, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        with torch.no_grad():
+            zr.copy_(to_gpu(z0r)); zi.copy_(to_gpu(z0i))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.run(gc_r, gc_i, zr, zi, status=st)
+        stream.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays
+        assert bits_equal(to_np(zr), wr) and bits_equal(to_np(zi), wi), rep
+        assert int(to_np(st).sum()) == 0
+
+
+def test_dk_known_roots_and_status():
+    K = 4
+    deg, cre, cim, known = synth.dk_batch(K, 6, 16, 40, seed=50, n_known=4, known_degree=16)
+    zr = torch.zeros((K, int(deg.sum())), dtype=torch.float64, device="cuda")
+    zi = torch.zeros_like(zr)
+    plan = mpx.RootsPlan("qd", deg, iters=200, init=True, graph=False)
+    st = plan.run(to_gpu(cre), to_gpu(cim), zr, zi)
+    assert int(to_np(st).sum()) == 0
+    r, i = to_np(zr), to_np(zi)
+    _, roff = synth.offsets(deg)
+    for b in range(4):
+        z = r[0, roff[b]:roff[b + 1]] + 1j * i[0, roff[b]:roff[b + 1]]
+        for w in known[b]:
+            assert np.min(np.abs(z - w)) < 1e-13
+    # coincident start values -> non-finite -> status 1
+    dz = np.array([3], np.int32)
+    _, c2r, c2i = _dk_inputs(K, dz, 60)
+    sr = np.zeros((K, 3)); si = np.zeros((K, 3))
+    sr[0] = [0.5, 0.5, -0.3]
+    zr2, zi2 = to_gpu(sr), to_gpu(si)
+    st2 = mpx.RootsPlan("qd", dz, iters=2, init=False, graph=False).run(to_gpu(c2r), to_gpu(c2i), zr2, zi2)
+    assert int(to_np(st2)[0]) == 1
+
+
+def test_dk_full_batch_sampled_bit_exact():
+    """Full-size batch (4096 QD polynomials, degrees 16..512, 200 sweeps, one
+    persistent launch): polynomials of degree <= 40 sampled and re-run one by
+    one in the oracle from the same start values must match bit for bit."""
+    K = 4
+    deg, cre, cim, known = synth.dk_batch(K, 4096, 16, 512, seed=synth.seed_for(2, 0), n_known=16)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    plan = mpx.RootsPlan("qd", deg, iters=200, init=False, graph=True)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        st = plan.run(to_gpu(cre), to_gpu(cim), zr, zi)
+    stream.synchronize()
+    r, i, s = to_np(zr), to_np(zi), to_np(st)
+    coff, roff = synth.offsets(deg)
+    small = [b for b in range(16, 4096) if deg[b] <= 40][:4] + [0, 1]
+    for b in small:
+        cs = slice(coff[b], coff[b + 1]); rs = slice(roff[b], roff[b + 1])
+        wr, wi, ws = oracle.polyroots(K, deg[b:b + 1], cre[:, cs], cim[:, cs],
+                                      z0r[:, rs], z0i[:, rs], iters=200, init=False)
+        assert bits_equal(np.ascontiguousarray(r[:, rs]), wr), b
+        assert bits_equal(np.ascontiguousarray(i[:, rs]), wi), b
+        assert s[b] == ws[0]
+    for b in range(16):
+        z = r[0, roff[b]:roff[b + 1]] + 1j * i[0, roff[b]:roff[b + 1]]
+        for w in known[b]:
+            assert np.min(np.abs(z - w)) < 1e-12, b

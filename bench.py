@@ -1,22 +1,35 @@
-"""Benchmark: branch-free multicomponent GEMM on one MI355X.
+"""Benchmark of the branch-free multicomponent kernels on one MI355X.
 
-Headline workload: square QD GEMM, m = n = k = 2048, entries generated as in
-the seeded uniform recipe (leading component U[-1, 1), lower components
-scaled by 2^-53 u and made non-overlapping).  One step = one C = A B.
-Throughput is reported in multicomponent operations per second
-(2 m n k: one BF multiply and one BF add per multiply-add) and as a fraction
-of the FP64 vector issue peak (each BF op is a fixed count of FP64 VALU
-instructions: QD multiply-add = 209).
+Headline (the `value` of the JSON line): square QD GEMM, m = n = k = 2048,
+seeded uniform inputs (leading component U[-1, 1), lower components the
+previous one times 2^-53 u, made non-overlapping).  One step = one C = A B.
+Throughput in multicomponent operations per second (2 m n k: one BF multiply
+and one BF add per multiply-add), and as a fraction of the FP64 VALU issue
+peak (a QD multiply-add is 209 FP64 VALU instructions; peak = 256 CUs x 64
+lanes x 2.4 GHz = 39.3 T lane-instructions/s).  The kernel time comes from
+HIP events recorded on the stream the kernel is launched on.
 
-Printed JSON line (one): metric/value/unit, ms_per_step, roofline of the
-GEMM kernel (HIP-event timing on the launch stream), the CPU oracle timed on
-a bounded row sample of the same product, and secondary rows (TD / DD / FF
-GEMM at 2048) for context.
+The same line carries, under "rows", the other rows of the hot path, each
+measured on its own synthetic workload:
+  gemm          DD / TD / QD at 512, 1024, 2048 and FF at 2048;
+  gemv          n = 8192 (QD, TD, DD);
+  vector        AXPY and dot at n = 4096 (latency) and n = 2^24 (HBM);
+  durand_kerner 4096 complex QD polynomials, degrees 16..512, 200 sweeps
+                in one graph-replayed persistent launch: roots/s, residual,
+                error on 16 known-root polynomials;
+  autograd      QD and DD GEMM 2048 forward + backward, Horner backward
+                (degree 1024, batch 1024);
+  ozaki         Ozaki-split DD GEMM on FP64 MFMA vs the branch-free DD GEMM
+                at n = 4096 (and 8192 with --full), phi = 1, 4, 8, slices
+                chosen as the fewest meeting the DD bound n 2^-104 sum|ab|.
+and "cpu_baseline": the CPU oracle on a bounded row sample of the headline
+product.  --quick skips the rows.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -26,10 +39,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 VALU instructions per multiply-add (BF mul + BF add), from Tables 1-2
-# and the double-word algorithms: DD 9 + 20, TD 39 + 57, QD 106 + 103.
+# FP64 (FP32 for FF) VALU instructions per multiply-add: BF mul + BF add
+# (Tables 1-2 and the double-word algorithms): DD 9 + 20, TD 39 + 57, QD 106 + 103.
 INSTR_PER_MAC = {"dd": 29, "td": 96, "qd": 209, "ff": 29}
-PEAK_ISSUE_TOPS = 256 * 64 * 2.4e9 / 1e12       # FP64 (and non-packed FP32) lane-ops/s: 39.3 T
+FLOP_PER_MAC = {"dd": 30, "td": 99, "qd": 215, "ff": 30}   # FMA counted as 2
+PEAK_F64_ISSUE = 256 * 64 * 2.4e9            # 39.3e12 FP64 lane-instructions/s
+PEAK_F32_ISSUE = 2 * PEAK_F64_ISSUE          # binary32 VALU issues at twice the FP64 rate
+PEAK_F64_FLOP = 78.6e12
+PEAK_MFMA_F64 = 78.6e12
+PEAK_HBM = 8.0e12
 METRIC = "TD/QD GEMM mp-op/s & % FP64 peak; Ozaki-MFMA vs branch-free DD at equal error"
 
 
@@ -40,34 +58,61 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--prec", default="qd")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the secondary precisions")
+    ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
+    ap.add_argument("--full", action="store_true", help="also the n = 8192 Ozaki comparison")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 512 MiB read + 512 MiB write kernel (counter calibration)")
     return ap.parse_args()
 
 
-def time_gemm(mpx, torch, p, n, steps, warmup, seed_base):
+class Timer:
+    """Mean time per call (ms) of fn() over `reps`, HIP events on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __call__(self, fn, reps=3, warmup=1):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gpu_mp(torch, K, shape, seed, dist="U", phi=4.0, dtype=np.float64):
     from paper_2603_14926_amd import synth
+    return torch.from_numpy(synth.mp_array(K, shape, seed, dist, phi=phi, dtype=dtype)).cuda()
+
+
+# ------------------------------------------------------------------ GEMM ----
+
+def gemm_row(mpx, torch, T, p, n, reps):
     dt = np.float32 if p == "ff" else np.float64
     K = mpx.ncomp(p)
-    A = torch.from_numpy(synth.mp_array(K, (n, n), synth.seed_for(1, seed_base), "U", dtype=dt)).cuda()
-    B = torch.from_numpy(synth.mp_array(K, (n, n), synth.seed_for(1, seed_base + 1), "U", dtype=dt)).cuda()
+    from paper_2603_14926_amd import synth
+    A = gpu_mp(torch, K, (n, n), synth.seed_for(1, 0), dtype=dt)
+    B = gpu_mp(torch, K, (n, n), synth.seed_for(1, 1), dtype=dt)
     Cm = torch.empty_like(A)
-    mpx.gemm_autotune(p, A, B, Cm, reps=1)
-    for _ in range(warmup):
-        mpx.gemm(p, A, B, out=Cm)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
-        mpx.gemm(p, A, B, out=Cm)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_kernel = e0.elapsed_time(e1) / steps
-    return ms_kernel, wall / steps * 1e3, (A, B, Cm)
+    v, _ = mpx.gemm_autotune(p, A, B, Cm, reps=1)
+    ms = T(lambda: mpx.gemm(p, A, B, out=Cm), reps=reps)
+    macs = float(n) ** 3
+    peak = PEAK_F32_ISSUE if p == "ff" else PEAK_F64_ISSUE
+    return {"ms": ms, "mp_op_s": 2 * macs / (ms * 1e-3),
+            "frac_issue_peak": macs * INSTR_PER_MAC[p] / (ms * 1e-3) / peak,
+            "variant": mpx.gemm_variants(p)[v]}
 
 
 def cpu_baseline(p, n, target_s=12.0):
@@ -84,75 +129,317 @@ def cpu_baseline(p, n, target_s=12.0):
     t0 = time.perf_counter()
     oracle.gemm(K, A[:, :rows, :], B)
     dt = time.perf_counter() - t0
-    # grow the sample to roughly target_s of work
-    scale = max(1, int(target_s / max(dt, 1e-3)))
-    rows2 = min(n, rows * scale)
+    rows2 = min(n, rows * max(1, int(target_s / max(dt, 1e-3))))
     rows2 = max(threads, (rows2 // threads) * threads)
     t0 = time.perf_counter()
     oracle.gemm(K, A[:, :rows2, :], B)
     dt = time.perf_counter() - t0
     macs = rows2 * n * n
-    return {
-        "value": 2.0 * macs / dt,
-        "unit": "mp-op/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"{p.upper()} GEMM rows 0..{rows2 - 1} of the {n}x{n}x{n} product "
-                  f"({rows2}x{n}x{n} multiply-adds, {dt:.1f} s)",
-    }
+    return {"value": 2.0 * macs / dt, "unit": "mp-op/s", "cores": threads, "kind": "oracle",
+            "sample": f"{p.upper()} GEMM rows 0..{rows2 - 1} of the {n}x{n}x{n} product "
+                      f"({rows2}x{n}x{n} multiply-adds in {dt:.1f} s)"}
+
+
+# -------------------------------------------------------- GEMV and vector ----
+
+def gemv_rows(mpx, torch, T):
+    from paper_2603_14926_amd import synth
+    out = {}
+    n = 8192
+    A4 = gpu_mp(torch, 4, (n, n), synth.seed_for(1, 20))
+    x4 = gpu_mp(torch, 4, n, synth.seed_for(1, 21))
+    for p in ("qd", "td", "dd"):
+        K = mpx.ncomp(p)
+        A, x = A4[:K], x4[:K]      # the leading K components are a K-component input
+        y = torch.empty((K, n), dtype=torch.float64, device="cuda")
+        ws = mpx.workspace(mpx.OP_GEMV, p, n, n, 0)
+        ms = T(lambda: mpx.gemv(p, A, x, out=y, ws=ws), reps=5)
+        macs = float(n) * n
+        bytes_ = K * 8.0 * (n * n + 2 * n)
+        out[p] = {"ms": ms, "mp_op_s": 2 * macs / (ms * 1e-3),
+                  "GB_s": bytes_ / (ms * 1e-3) / 1e9, "frac_hbm_peak": bytes_ / (ms * 1e-3) / PEAK_HBM,
+                  "frac_issue_peak": macs * INSTR_PER_MAC[p] / (ms * 1e-3) / PEAK_F64_ISSUE}
+    del A4, x4
+    return out
+
+
+def vector_rows(mpx, torch, T):
+    from paper_2603_14926_amd import synth
+    out = {}
+    for p in ("qd", "td", "dd"):
+        K = mpx.ncomp(p)
+        row = {}
+        for n in (4096, 1 << 24):
+            x = gpu_mp(torch, K, n, synth.seed_for(0, 1))
+            y = gpu_mp(torch, K, n, synth.seed_for(0, 2))
+            alpha = [0.75] + [0.0] * (K - 1)
+            r = torch.empty(K, dtype=torch.float64, device="cuda")
+            ws = mpx.workspace(mpx.OP_DOT, p, n)
+            reps = 200 if n == 4096 else 10
+            t_axpy = T(lambda: mpx.axpy(p, alpha, x, y), reps=reps)
+            t_dot = T(lambda: mpx.dot(p, x, y, out=r, ws=ws), reps=reps)
+            b_axpy, b_dot = 3 * K * 8.0 * n, 2 * K * 8.0 * n
+            row[str(n)] = {
+                "axpy_us": t_axpy * 1e3, "axpy_GB_s": b_axpy / (t_axpy * 1e-3) / 1e9,
+                "axpy_frac_hbm": b_axpy / (t_axpy * 1e-3) / PEAK_HBM,
+                "dot_us": t_dot * 1e3, "dot_GB_s": b_dot / (t_dot * 1e-3) / 1e9,
+                "dot_frac_hbm": b_dot / (t_dot * 1e-3) / PEAK_HBM,
+            }
+        out[p] = row
+    return out
+
+
+# --------------------------------------------------------- Durand-Kerner ----
+
+def dk_residual(deg, cre, cim, zr, zi, polys):
+    """max_i |q(z_i)| / sum_k |c_k| |z_i|^k over the roots of the given
+    polynomials (binary64 from the leading components; z scaled by
+    max(1, |z|) so degree-512 values do not overflow)."""
+    from paper_2603_14926_amd import synth
+    coff, roff = synth.offsets(deg)
+    worst_small, worst = 0.0, 0.0
+    for b in polys:
+        n = int(deg[b])
+        a = cre[0, coff[b]:coff[b + 1]] + 1j * cim[0, coff[b]:coff[b + 1]]
+        c = a / a[-1]
+        z = zr[0, roff[b]:roff[b + 1]] + 1j * zi[0, roff[b]:roff[b + 1]]
+        if not np.all(np.isfinite(z)):
+            return float("nan"), float("nan")
+        s = np.maximum(1.0, np.abs(z))
+        w = z / s
+        num = np.ones_like(z)
+        den = np.ones(z.shape)
+        inv = 1.0 / s
+        scale = np.ones(z.shape)
+        for k in range(n - 1, -1, -1):
+            scale = scale * inv
+            num = num * w + c[k] * scale
+            den = den * np.abs(w) + abs(c[k]) * scale
+        r = float(np.max(np.abs(num) / den))
+        worst = max(worst, r)
+        if n <= 24:
+            worst_small = max(worst_small, r)
+    return worst, worst_small
+
+
+def dk_row(mpx, torch, T):
+    from paper_2603_14926_amd import synth
+    K = 4
+    deg, cre, cim, known = synth.dk_batch(K, 4096, 16, 512, seed=synth.seed_for(2, 0), n_known=16)
+    total_roots = int(deg.sum())
+    gcr, gci = torch.from_numpy(cre).cuda(), torch.from_numpy(cim).cuda()
+    zr = torch.zeros((K, total_roots), dtype=torch.float64, device="cuda")
+    zi = torch.zeros_like(zr)
+    # start values (Aberth) from a 0-sweep init plan, then the timed 200-sweep plan
+    mpx.RootsPlan("qd", deg, iters=0, init=True, graph=False).run(gcr, gci, zr, zi)
+    z0r, z0i = zr.clone(), zi.clone()
+    plan = mpx.RootsPlan("qd", deg, iters=200, init=False, graph=True)
+    variant, probe_ms = plan.autotune(gcr, gci, z0r, z0i, iters_probe=2)
+    stream = torch.cuda.Stream()
+    st = torch.zeros(deg.size, dtype=torch.int32, device="cuda")
+    times = []
+    for rep in range(2):
+        zr.copy_(z0r); zi.copy_(z0i)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.run(gcr, gci, zr, zi, status=st)
+            e1.record(stream)
+        stream.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = min(times)
+    r, i = zr.cpu().numpy(), zi.cpu().numpy()
+    sample = list(range(16)) + list(range(16, deg.size, 16))
+    worst, worst_small = dk_residual(deg, cre, cim, r, i, sample)
+    _, roff = synth.offsets(deg)
+    kerr = 0.0
+    for b in range(16):
+        z = r[0, roff[b]:roff[b + 1]] + 1j * i[0, roff[b]:roff[b + 1]]
+        kerr = max(kerr, max(float(np.min(np.abs(z - w))) for w in known[b]))
+    n2 = float((deg.astype(np.float64) ** 2).sum())
+    instr = 1672.0 * n2 * 200          # ~1672 FP64 VALU instr per root pair per sweep (QD)
+    return {"polys": int(deg.size), "roots": total_roots, "sweeps": 200, "ms": ms,
+            "roots_per_s": total_roots / (ms * 1e-3),
+            "frac_issue_peak_est": instr / (ms * 1e-3) / PEAK_F64_ISSUE,
+            "variant": int(variant), "nonfinite_polys": int(st.sum().item()),
+            "max_residual": worst, "max_residual_deg_le_24": worst_small,
+            "residual_sample": f"{len(sample)} polynomials (16 known-root + every 16th)",
+            "known_root_max_error": kerr}
+
+
+# -------------------------------------------------------------- autograd ----
+
+def autograd_row(mpx, torch, T):
+    from paper_2603_14926_amd import autograd as ag, synth
+    out = {}
+    n = 2048
+    for p in ("qd", "dd"):
+        K = mpx.ncomp(p)
+        A = gpu_mp(torch, K, (n, n), synth.seed_for(3, 0)).requires_grad_(True)
+        B = gpu_mp(torch, K, (n, n), synth.seed_for(3, 1)).requires_grad_(True)
+        G = gpu_mp(torch, K, (n, n), synth.seed_for(3, 2))
+
+        def step():
+            A.grad = None; B.grad = None
+            ag.gemm(A, B, p).backward(G)
+        ms = T(step, reps=2)
+        macs = 3.0 * n ** 3
+        out[f"{p}_gemm_fwd_bwd_{n}"] = {"ms": ms, "mp_op_s": 2 * macs / (ms * 1e-3),
+                                        "frac_issue_peak": macs * INSTR_PER_MAC[p] / (ms * 1e-3) / PEAK_F64_ISSUE}
+    K, batch, deg = 4, 1024, 1024
+    coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(3, 10)).requires_grad_(True)
+    x = gpu_mp(torch, K, batch, synth.seed_for(3, 11)).requires_grad_(True)
+    g = gpu_mp(torch, K, batch, synth.seed_for(3, 12))
+    ms_f = T(lambda: ag.polyval(coef, x, "qd"), reps=5)
+
+    def hstep():
+        coef.grad = None; x.grad = None
+        ag.polyval(coef, x, "qd").backward(g)
+    ms_fb = T(hstep, reps=5)
+    out["qd_horner_1024x1024"] = {"fwd_ms": ms_f, "fwd_bwd_ms": ms_fb}
+    return out
+
+
+# ----------------------------------------------------------------- Ozaki ----
+
+def rel_errors(A, B, Cm, rows, cols):
+    """max over sampled entries of |C - exact| / sum |a b| (exact rationals)."""
+    from oracle import exact
+    worst = 0.0
+    for i, j in zip(rows, cols):
+        a = np.ascontiguousarray(A[:, i, :]); b = np.ascontiguousarray(B[:, :, j])
+        ex = exact.dot(a, b)
+        sc = exact.abs_dot(a, b)
+        worst = max(worst, float(abs(exact.value(Cm[:, i, j]) - ex)) / sc)
+    return worst
+
+
+def ozaki_row(mpx, torch, T, sizes):
+    from paper_2603_14926_amd import synth
+    out = {}
+    rng = np.random.default_rng(11)
+    for n in sizes:
+        for phi in (1.0, 4.0, 8.0):
+            log(f"ozaki n={n} phi={phi}")
+            A_np = synth.mp_array(2, (n, n), synth.seed_for(4, int(phi)), "W", phi=phi)
+            B_np = synth.mp_array(2, (n, n), synth.seed_for(4, 10 + int(phi)), "W", phi=phi)
+            A, B = torch.from_numpy(A_np).cuda(), torch.from_numpy(B_np).cuda()
+            rows = rng.integers(0, n, 12); cols = rng.integers(0, n, 12)
+            Cbf = torch.empty_like(A)
+            mpx.gemm_autotune("dd", A, B, Cbf, reps=1)
+            t_bf = T(lambda: mpx.gemm("dd", A, B, out=Cbf), reps=2)
+            err_bf = rel_errors(A_np, B_np, Cbf.cpu().numpy(), rows, cols)
+            bound = n * 2.0 ** -104
+            chosen, sweep = None, {}
+            Coz = torch.empty_like(A)
+            for s in range(4, 13):
+                ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
+                mpx.gemm_ozaki_dd(A, B, s, out=Coz, ws=ws)
+                err = rel_errors(A_np, B_np, Coz.cpu().numpy(), rows, cols)
+                sweep[s] = err
+                if err <= bound and chosen is None:
+                    chosen = s
+                if err <= err_bf:
+                    break
+                del ws
+            s_eq = min((s for s, e in sweep.items() if e <= err_bf), default=None)
+            res = {"bf_dd_ms": t_bf, "bf_dd_max_rel_err": err_bf, "bound": bound,
+                   "error_by_slices": {str(k): v for k, v in sweep.items()}}
+            for tag, s in (("at_bound", chosen), ("at_bf_error", s_eq)):
+                if s is None:
+                    continue
+                ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
+                t = T(lambda: mpx.gemm_ozaki_dd(A, B, s, out=Coz, ws=ws), reps=2)
+                prods = s * (s + 1) / 2
+                res[tag] = {"slices": s, "ms": t, "max_rel_err": sweep[s],
+                            "frac_mfma_peak": prods * 2.0 * n ** 3 / (t * 1e-3) / PEAK_MFMA_F64,
+                            "speedup_vs_bf_dd": t_bf / t}
+                del ws
+            out[f"n{n}_phi{int(phi)}"] = res
+            del A, B, Cbf, Coz
+            torch.cuda.empty_cache()
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the kernels are "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the kernels are "
               f"single-GPU and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2603_14926_amd import mpx
+    from paper_2603_14926_amd import mpx, synth
     mpx.lib()
+    T = Timer(torch)
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     p, n = args.prec, args.n
-    ms, wall_ms, _ = time_gemm(mpx, torch, p, n, args.steps, args.warmup, 0)
+    K = mpx.ncomp(p)
+    dt = np.float32 if p == "ff" else np.float64
+    log(f"headline {p} gemm n={n}")
+    A = gpu_mp(torch, K, (n, n), synth.seed_for(1, 0), dtype=dt)
+    B = gpu_mp(torch, K, (n, n), synth.seed_for(1, 1), dtype=dt)
+    Cm = torch.empty_like(A)
+    variant, _ = mpx.gemm_autotune(p, A, B, Cm, reps=1)
+    for _ in range(args.warmup):
+        mpx.gemm(p, A, B, out=Cm)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        mpx.gemm(p, A, B, out=Cm)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    ms = e0.elapsed_time(e1) / args.steps
     macs = float(n) ** 3
-    value = 2.0 * macs / (ms * 1e-3)
-    achieved = macs * INSTR_PER_MAC[p] / (ms * 1e-3) / 1e12
-    flops_per_mac = {"dd": 30, "td": 99, "qd": 215, "ff": 30}[p]
+    peak = PEAK_F32_ISSUE if p == "ff" else PEAK_F64_ISSUE
+    achieved = macs * INSTR_PER_MAC[p] / (ms * 1e-3)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": 2.0 * macs / (ms * 1e-3),
         "unit": "mp-op/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "wall_ms_per_step": wall_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "wall_ms_per_step": wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if p == "ff" else "f64",
-        "data": "synthetic (seeded SplitMix64, uniform leading component)",
-        "config": {"workload": f"{p}_gemm_{n}", "precision": p.upper(), "m": n, "n": n, "k": n,
-                   "variant": "autotuned"},
+        "data": "synthetic (seeded SplitMix64; uniform leading component, non-overlapping lower components)",
+        "config": {"workload": f"{p}_gemm_{n}x{n}x{n}", "precision": p.upper(), "m": n, "n": n, "k": n,
+                   "kernel_variant": mpx.gemm_variants(p)[variant]},
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_ISSUE_TOPS,
-            "unit": "TOP/s (FP64 VALU lane-instructions)",
-            "frac": achieved / PEAK_ISSUE_TOPS,
-            "frac_fp64_flop_peak": macs * flops_per_mac / (ms * 1e-3) / 78.6e12,
+            "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "T FP64 VALU lane-instructions/s" if p != "ff" else "T FP32 VALU lane-instructions/s",
+            "frac": achieved / peak,
+            "frac_fp64_flop_peak": macs * FLOP_PER_MAC[p] / (ms * 1e-3) / PEAK_F64_FLOP,
             "traffic": None,
         },
     }
-    if not args.no_extra:
+    del A, B, Cm
+    if not args.quick:
         rows = {}
-        for q in ("td", "dd", "ff"):
-            if q == p:
-                continue
-            qms, _, _ = time_gemm(mpx, torch, q, n, max(3, args.steps // 2), 1, 10)
-            rows[q] = {"ms": qms, "mp_op_s": 2.0 * macs / (qms * 1e-3),
-                       "frac_issue_peak": macs * INSTR_PER_MAC[q] / (qms * 1e-3) / 1e12 / PEAK_ISSUE_TOPS}
-        out["other_precisions_gemm_2048"] = rows
-    if not args.no_cpu and p != "ff":
+        log("gemm rows")
+        g = {}
+        for q in ("qd", "td", "dd"):
+            for nn in (512, 1024, 2048):
+                g[f"{q}_{nn}"] = gemm_row(mpx, torch, T, q, nn, reps=5 if nn < 2048 else 3)
+        g["ff_2048"] = gemm_row(mpx, torch, T, "ff", 2048, reps=3)
+        rows["gemm"] = g
+        log("gemv rows"); rows["gemv_8192"] = gemv_rows(mpx, torch, T)
+        log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
+        log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
+        log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
+        rows["ozaki"] = ozaki_row(mpx, torch, T, (4096, 8192) if args.full else (4096,))
+        out["rows"] = rows
+    if not args.no_cpu and not args.quick and p != "ff":
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(p, n)
     print(json.dumps(out), flush=True)
 

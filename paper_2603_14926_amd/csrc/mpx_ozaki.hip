@@ -126,7 +126,7 @@ k_oz_split_b(long long k, long long n, const double* __restrict__ B, long long l
 //
 // v_mfma_f64_16x16x4_f64 operand layout (wave64): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16] of the 16x4 and 4x16 operands and
-// holds D[4 (l / 16) + v][l % 16], v = 0..3, of the 16x16 result.
+// holds D[l / 16 + 4 v][l % 16], v = 0..3, of the 16x16 result.
 template <int S, int TA, int TB>
 __global__ void __launch_bounds__(OZ_THREADS)
 k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, long long kp,
@@ -206,7 +206,7 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
                 const int fj = j < n ? f[j] : 0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const long long i = m0 + wr + 16 * a + 4 * lk + v;
+                    const long long i = m0 + wr + 16 * a + lk + 4 * v;
                     const int ei = i < m ? e[i] : 0;
 #pragma unroll
                     for (int g = 0; g < S; ++g) {
@@ -227,7 +227,7 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
             const long long j = n0 + wc + 16 * b + lr;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const long long i = m0 + wr + 16 * a + 4 * lk + v;
+                const long long i = m0 + wr + 16 * a + lk + 4 * v;
                 if (i < m && j < n) mp_store<double, 2>(C, psC, i * ldc + j, dd[a][b][v]);
             }
         }
@@ -272,9 +272,11 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     k_oz_col_exp<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(k, n, B, ldb, f);
     if ((st = launch_status())) return st;
     const long long ta = d.mp * d.kp, tb = d.kp * d.np;
+    if (ta > 0)
     k_oz_split_a<S><<<(unsigned)std::min<long long>(ceil_div(ta, 256), 65536), 256, 0, s>>>(
         m, k, A, lda, psA, e, beta, SA, d.mp, d.kp);
     if ((st = launch_status())) return st;
+    if (tb > 0)
     k_oz_split_b<S><<<(unsigned)std::min<long long>(ceil_div(tb, 256), 65536), 256, 0, s>>>(
         k, n, B, ldb, psB, f, beta, SB, d.kp, d.np);
     if ((st = launch_status())) return st;

@@ -46,7 +46,8 @@ def test_ozaki_4096_sampled_error_and_parity(phi):
     A = synth.mp_array(2, (n, n), synth.seed_for(4, int(phi)), "W", phi=phi)
     B = synth.mp_array(2, (n, n), synth.seed_for(4, 10 + int(phi)), "W", phi=phi)
     got = to_np(mpx.gemm_ozaki_dd(to_gpu(A), to_gpu(B), s, beta=20, kblk=256))
-    rows = np.array([0, 5, 2048, 4095]); cols = np.array([4095, 77, 2048, 0])
+    # rows cover every position inside a 16-row MFMA tile and the tile edges
+    rows = np.array([0, 1, 2, 3, 4, 7, 9, 14, 15, 2049, 4094, 4095]); cols = np.array([4095, 77, 2048, 0, 31, 16, 1, 2, 3, 4094, 5, 17])
     want = oracle.ozaki_entries(A, B, rows, cols, s=s, beta=20, kblk=256)
     assert bits_equal(np.ascontiguousarray(got[:, rows, cols]), want)
     for t in range(rows.size):

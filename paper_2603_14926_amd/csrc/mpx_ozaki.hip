@@ -32,6 +32,7 @@
 namespace mpx {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 constexpr int OZ_BM = 64, OZ_BN = 64, OZ_KT = 8, OZ_THREADS = 256;
 constexpr int OZ_MAX_S = 12;
@@ -78,8 +79,9 @@ __device__ __forceinline__ void split_dd(double hi, double lo, int e, int beta, 
     }
 }
 
-// Slices of A into SA[p][i][l] (planes of mp x kp, row-major), of B into
-// SB[p][l][j] (planes of kp x np); padding rows / columns are zero.
+// Slices of A into SA[p][l][i] (planes of kp x mp: k-major, so a 64-row A
+// panel of one k is contiguous), of B into SB[p][l][j] (planes of kp x np);
+// padding rows / columns are zero.
 template <int S>
 __global__ void __launch_bounds__(256)
 k_oz_split_a(long long m, long long k, const double* __restrict__ A, long long lda,
@@ -88,7 +90,7 @@ k_oz_split_a(long long m, long long k, const double* __restrict__ A, long long l
     const long long total = mp * kp;
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total;
          t += (long long)gridDim.x * 256) {
-        const long long i = t / kp, l = t % kp;
+        const long long l = t / mp, i = t % mp;
         double sl[S];
         if (i < m && l < k) {
             split_dd<S>(A[i * lda + l], A[psA + i * lda + l], e[i], beta, sl);
@@ -127,16 +129,24 @@ k_oz_split_b(long long k, long long n, const double* __restrict__ B, long long l
 // v_mfma_f64_16x16x4_f64 operand layout (wave64): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16] of the 16x4 and 4x16 operands and
 // holds D[l / 16 + 4 v][l % 16], v = 0..3, of the 16x16 result.
+//
+// Workgroup = 2 x 2 waves, each wave TA x TB MFMA tiles (16 x 16 each).  Per
+// stage of OZ_KT = 8 k values the S slice panels of A (k-major, 8 x BM) and B
+// (8 x BN) are copied into LDS with 16-byte loads that were issued one stage
+// ahead (register prefetch).  LDS rows are padded by 16 doubles so the four
+// k rows a wave reads at once fall in different bank halves.
 template <int S, int TA, int TB>
 __global__ void __launch_bounds__(OZ_THREADS)
 k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, long long kp,
           const double* __restrict__ SA, const double* __restrict__ SB,
           const int* __restrict__ e, const int* __restrict__ f, int beta, long long kblk,
           double* __restrict__ C, long long ldc, long long psC, int tiles_n) {
-    constexpr int BM = 32 * TA, BN = 32 * TB;  // 2 x 2 waves of TA x TB MFMA tiles
-    constexpr int LA = OZ_KT + 1;              // padded LDS row of the A panel
-    __shared__ double sA[S][BM][LA];
-    __shared__ double sB[S][OZ_KT][BN];
+    constexpr int BM = 32 * TA, BN = 32 * TB;
+    constexpr int LDA = BM + 16, LDB = BN + 16;
+    constexpr int A_V2 = (S * OZ_KT * BM / 2 + OZ_THREADS - 1) / OZ_THREADS;
+    constexpr int B_V2 = (S * OZ_KT * BN / 2 + OZ_THREADS - 1) / OZ_THREADS;
+    __shared__ __attribute__((aligned(16))) double sA[S][OZ_KT][LDA];
+    __shared__ __attribute__((aligned(16))) double sB[S][OZ_KT][LDB];
 
     const int tile = blockIdx.x;
     const long long m0 = (long long)(tile / tiles_n) * BM;
@@ -160,44 +170,51 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
 #pragma unroll
             for (int v = 0; v < 4; ++v) dd[a][b][v] = mp_zero<double, 2>();
 
+    // Staging: thread tid moves 16-byte pairs v = tid + it*256 of the A panel
+    // (S slices x 8 k x BM rows) and the B panel (S x 8 x BN).  When the count
+    // is not a multiple of 256 the last pairs are clamped: two threads then copy
+    // the same pair to the same place (no condition, so the prefetch registers
+    // stay in VGPRs).
     const long long plA = mp * kp, plB = kp * np;
-    for (long long kb = 0; kb < k; kb += kblk) {
-        const long long kend = kb + kblk < kp ? kb + kblk : kp;
-        for (long long kc = kb; kc < kend; kc += OZ_KT) {
-            __syncthreads();
-            // stage the S slice panels: A 64 x 8, B 8 x 64 per slice
-            for (int t = tid; t < S * BM * OZ_KT; t += OZ_THREADS) {
-                const int p = t / (BM * OZ_KT), r = (t / OZ_KT) % BM, c = t % OZ_KT;
-                sA[p][r][c] = SA[p * plA + (m0 + r) * kp + kc + c];
-            }
-            for (int t = tid; t < S * OZ_KT * BN; t += OZ_THREADS) {
-                const int p = t / (OZ_KT * BN), r = (t / BN) % OZ_KT, c = t % BN;
-                sB[p][r][c] = SB[p * plB + (kc + r) * np + n0 + c];
-            }
-            __syncthreads();
+    constexpr int NA = S * OZ_KT * BM / 2, NB = S * OZ_KT * BN / 2;
+    d2_t ra[A_V2], rb[B_V2];
+    int oa[A_V2], ob[B_V2];          // LDS double offsets
+    long long ga[A_V2], gb[B_V2];    // global offsets for k = 0
 #pragma unroll
-            for (int ks = 0; ks < OZ_KT; ks += 4) {
-                double fa[S][TA], fb[S][TB];
+    for (int it = 0; it < A_V2; ++it) {
+        int v = tid + it * OZ_THREADS;
+        v = v < NA ? v : NA - 1;
+        const int p = v / (OZ_KT * BM / 2), rem = v % (OZ_KT * BM / 2);
+        const int kk = rem / (BM / 2), i2 = rem % (BM / 2);
+        oa[it] = (p * OZ_KT + kk) * LDA + 2 * i2;
+        ga[it] = p * plA + (long long)kk * mp + m0 + 2 * i2;
+    }
 #pragma unroll
-                for (int p = 0; p < S; ++p) {
+    for (int it = 0; it < B_V2; ++it) {
+        int v = tid + it * OZ_THREADS;
+        v = v < NB ? v : NB - 1;
+        const int p = v / (OZ_KT * BN / 2), rem = v % (OZ_KT * BN / 2);
+        const int kk = rem / (BN / 2), j2 = rem % (BN / 2);
+        ob[it] = (p * OZ_KT + kk) * LDB + 2 * j2;
+        gb[it] = p * plB + (long long)kk * np + n0 + 2 * j2;
+    }
+    auto fetch = [&](long long kc) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int a = 0; a < TA; ++a) fa[p][a] = sA[p][wr + 16 * a + lr][ks + lk];
+        for (int it = 0; it < A_V2; ++it)
+            ra[it] = *reinterpret_cast<const d2_t*>(SA + ga[it] + kc * mp);
 #pragma unroll
-                    for (int b = 0; b < TB; ++b) fb[p][b] = sB[p][ks + lk][wc + 16 * b + lr];
-                }
+        for (int it = 0; it < B_V2; ++it)
+            rb[it] = *reinterpret_cast<const d2_t*>(SB + gb[it] + kc * np);
+    };
+    auto stash = [&]() __attribute__((always_inline)) {
 #pragma unroll
-                for (int p = 1; p <= S; ++p)
+        for (int it = 0; it < A_V2; ++it)
+            *reinterpret_cast<d2_t*>(&sA[0][0][0] + oa[it]) = ra[it];
 #pragma unroll
-                    for (int q = 1; q + p <= S + 1; ++q)
-#pragma unroll
-                        for (int a = 0; a < TA; ++a)
-#pragma unroll
-                            for (int b = 0; b < TB; ++b)
-                                acc[p + q - 2][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                    fa[p - 1][a], fb[q - 1][b], acc[p + q - 2][a][b], 0, 0, 0);
-            }
-        }
-        // fold the level sums of this k-block into the DD accumulators
+        for (int it = 0; it < B_V2; ++it)
+            *reinterpret_cast<d2_t*>(&sB[0][0][0] + ob[it]) = rb[it];
+    };
+    auto fold = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int a = 0; a < TA; ++a)
 #pragma unroll
@@ -219,6 +236,43 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
 #pragma unroll
                 for (int g = 0; g < S; ++g) acc[g][a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
             }
+    };
+
+    if (kp > 0) fetch(0);
+    for (long long kc = 0; kc < kp; kc += OZ_KT) {
+        __syncthreads();  // previous stage consumed
+        stash();
+        __syncthreads();
+        if (kc + OZ_KT < kp) fetch(kc + OZ_KT);  // in flight during the MFMAs below
+#pragma unroll
+        for (int ks = 0; ks < OZ_KT; ks += 4) {
+            double fb[S][TB];
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+#pragma unroll
+                for (int b = 0; b < TB; ++b) fb[q][b] = sB[q][ks + lk][wc + 16 * b + lr];
+#pragma unroll
+            for (int p = 0; p < S; ++p) {
+                double fa[TA];
+#pragma unroll
+                for (int a = 0; a < TA; ++a) fa[a] = sA[p][ks + lk][wr + 16 * a + lr];
+                // slice pairs (p+1, q+1) with p + q + 2 <= S + 1 feed level p + q
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    if (p + q < S) {
+#pragma unroll
+                        for (int a = 0; a < TA; ++a)
+#pragma unroll
+                            for (int b = 0; b < TB; ++b)
+                                acc[p + q][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                    fa[a], fb[q][b], acc[p + q][a][b], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // end of a k-block (blocks [0, kblk), [kblk, 2 kblk), ...; the padded
+        // tail beyond k holds zero slices): fold the level sums
+        if ((kc + OZ_KT) % kblk == 0 || kc + OZ_KT >= kp) fold();
     }
 #pragma unroll
     for (int a = 0; a < TA; ++a)
@@ -231,12 +285,11 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
                 if (i < m && j < n) mp_store<double, 2>(C, psC, i * ldc + j, dd[a][b][v]);
             }
         }
-    (void)mp;
 }
 
-// Wave tile in 16x16 MFMA tiles: 2 x 2 up to 6 slices, 2 x 1 beyond (the
+// Wave tile in 16x16 MFMA tiles: 2 x 1 up to 8 slices, 1 x 1 beyond (the
 // level accumulators, 4 doubles per tile and level, must fit the registers).
-constexpr int oz_tb(int S) { return S <= 6 ? 2 : 1; }
+constexpr int oz_ta(int S) { return S <= 8 ? 2 : 1; }
 
 struct OzDims {
     long long mp, np, kp;
@@ -280,9 +333,9 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     k_oz_split_b<S><<<(unsigned)std::min<long long>(ceil_div(tb, 256), 65536), 256, 0, s>>>(
         k, n, B, ldb, psB, f, beta, SB, d.kp, d.np);
     if ((st = launch_status())) return st;
-    constexpr int TB = oz_tb(S);
-    const int tn = (int)(d.np / (32 * TB)), tm = (int)(d.mp / 64);
-    k_oz_gemm<S, 2, TB><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
+    constexpr int TA = oz_ta(S);
+    const int tn = (int)(d.np / 32), tm = (int)(d.mp / (32 * TA));
+    k_oz_gemm<S, TA, 1><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
         m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
     return launch_status();
 }

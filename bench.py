@@ -88,6 +88,27 @@ class Timer:
         return e0.elapsed_time(e1) / reps
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the headline GEMM kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE, each scaled by the
+    same counter on a copy kernel of known size), or None when the summary is
+    missing, is for another workload, or was taken on different kernel
+    sources (SHA-256 prefix of the sources recorded with the counters)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["traffic_bytes"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -419,7 +440,9 @@ def main():
             "unit": "T FP64 VALU lane-instructions/s" if p != "ff" else "T FP32 VALU lane-instructions/s",
             "frac": achieved / peak,
             "frac_fp64_flop_peak": macs * FLOP_PER_MAC[p] / (ms * 1e-3) / PEAK_F64_FLOP,
-            "traffic": None,
+            "traffic": measured_traffic(f"{p}_gemm_{n}") if variant == 0 else None,
+            "traffic_unit": "bytes per launch (HBM fetch + write, rocprofv3 counters scaled by a copy kernel)",
+            "algorithmic_bytes": 3.0 * K * (4 if p == "ff" else 8) * n * n,
         },
     }
     del A, B, Cm

@@ -20,9 +20,9 @@
 //  * every C_ij is accumulated in ascending l from zero, exactly the naive
 //    triple loop's sequence, so results are bit-identical for every tiling.
 //
-// Workgroups are numbered so that the eight XCDs (which receive workgroups
-// round-robin) each get a contiguous band of tile rows: tiles that share an
-// A panel share an L2.
+// Workgroups are numbered so that each of the eight XCDs (which receive
+// workgroups round-robin) works on compact blocks of tiles whose A and B
+// panels stay in its L2.
 #include "mp_arith.hpp"
 #include "mpx_internal.hpp"
 
@@ -46,15 +46,24 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
     __shared__ T sA[K][BK][BM];
     __shared__ T sB[K][BK][BN];
 
-    // XCD-aware tile order: workgroup w runs on XCD w % 8; give each XCD a
-    // contiguous range of tile ids (row-major over the tile grid).
+    // XCD-aware tile order: workgroup w runs on XCD w % 8; each XCD gets a
+    // contiguous range of virtual tile ids, and virtual ids walk the tile grid
+    // in groups of 8 tile rows (column-major inside a group), so the
+    // workgroups resident on one XCD at a time cover a square block of C and
+    // share its A and B panels in that XCD's L2.
     const int w = blockIdx.x;
     const int per_xcd = (tiles_total + 7) / 8;
     const int xcd = w % 8, slot = w / 8;
-    int tile = xcd * per_xcd + slot;
-    if (per_xcd * 8 != tiles_total) tile = w;  // uneven split: plain order
-    const int m0 = (tile / tiles_n) * BM;
-    const int n0 = (tile % tiles_n) * BN;
+    int v = xcd * per_xcd + slot;
+    if (per_xcd * 8 != tiles_total) v = w;  // uneven split: plain order
+    constexpr int GROUP = 8;
+    const int tiles_m = tiles_total / tiles_n;
+    const int in_group = GROUP * tiles_n;
+    const int first_m = (v / in_group) * GROUP;
+    const int rows_here = tiles_m - first_m < GROUP ? tiles_m - first_m : GROUP;
+    const int r = v % in_group;
+    const int m0 = (first_m + r % rows_here) * BM;
+    const int n0 = (r / rows_here) * BN;
 
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;

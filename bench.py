@@ -20,8 +20,9 @@ measured on its own synthetic workload:
   autograd      QD and DD GEMM 2048 forward + backward, Horner backward
                 (degree 1024, batch 1024);
   ozaki         Ozaki-split DD GEMM on FP64 MFMA vs the branch-free DD GEMM
-                at n = 4096 (and 8192 with --full), phi = 1, 4, 8, slices
-                chosen as the fewest meeting the DD bound n 2^-104 sum|ab|.
+                at n = 4096 and 8192, phi = 1, 4, 8; slices chosen as the
+                fewest meeting the DD bound n 2^-104 sum|ab| ("at_bound")
+                and the BF DD GEMM's own measured error ("at_bf_error").
 and "cpu_baseline": the CPU oracle on a bounded row sample of the headline
 product.  --quick skips the rows.
 """
@@ -59,7 +60,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--prec", default="qd")
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
-    ap.add_argument("--full", action="store_true", help="also the n = 8192 Ozaki comparison")
+    ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 512 MiB read + 512 MiB write kernel (counter calibration)")
@@ -336,6 +337,12 @@ def rel_errors(A, B, Cm, rows, cols):
     return worst
 
 
+# Ozaki candidates in order of cost (slice-pair products s(s+1)/2): beta = 22
+# (22 bits per slice, exact level sums with kblk = 256 up to 6 slices), then
+# beta = 20 for more slices.
+OZAKI_CANDIDATES = [(4, 22), (5, 22), (6, 22), (7, 20), (8, 20), (9, 20), (10, 20), (11, 20), (12, 20)]
+
+
 def ozaki_row(mpx, torch, T, sizes):
     from paper_2603_14926_amd import synth
     out = {}
@@ -351,34 +358,37 @@ def ozaki_row(mpx, torch, T, sizes):
             mpx.gemm_autotune("dd", A, B, Cbf, reps=1)
             t_bf = T(lambda: mpx.gemm("dd", A, B, out=Cbf), reps=2)
             err_bf = rel_errors(A_np, B_np, Cbf.cpu().numpy(), rows, cols)
+            del Cbf
             bound = n * 2.0 ** -104
             chosen, sweep = None, {}
             Coz = torch.empty_like(A)
-            for s in range(4, 13):
+            for (s, beta) in OZAKI_CANDIDATES:
                 ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
-                mpx.gemm_ozaki_dd(A, B, s, out=Coz, ws=ws)
+                mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=256, out=Coz, ws=ws)
                 err = rel_errors(A_np, B_np, Coz.cpu().numpy(), rows, cols)
-                sweep[s] = err
+                sweep[(s, beta)] = err
+                del ws
                 if err <= bound and chosen is None:
-                    chosen = s
+                    chosen = (s, beta)
                 if err <= err_bf:
                     break
-                del ws
-            s_eq = min((s for s, e in sweep.items() if e <= err_bf), default=None)
+            s_eq = next(((s, b) for (s, b), e in sweep.items() if e <= err_bf), None)
             res = {"bf_dd_ms": t_bf, "bf_dd_max_rel_err": err_bf, "bound": bound,
-                   "error_by_slices": {str(k): v for k, v in sweep.items()}}
-            for tag, s in (("at_bound", chosen), ("at_bf_error", s_eq)):
-                if s is None:
+                   "error_by_slices": {f"s{s}_beta{b}": v for (s, b), v in sweep.items()},
+                   "sampled_entries": int(rows.size), "kblk": 256}
+            for tag, cfg in (("at_bound", chosen), ("at_bf_error", s_eq)):
+                if cfg is None:
                     continue
+                s, beta = cfg
                 ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
-                t = T(lambda: mpx.gemm_ozaki_dd(A, B, s, out=Coz, ws=ws), reps=2)
+                t = T(lambda: mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=256, out=Coz, ws=ws), reps=2)
                 prods = s * (s + 1) / 2
-                res[tag] = {"slices": s, "ms": t, "max_rel_err": sweep[s],
+                res[tag] = {"slices": s, "beta": beta, "ms": t, "max_rel_err": sweep[cfg],
                             "frac_mfma_peak": prods * 2.0 * n ** 3 / (t * 1e-3) / PEAK_MFMA_F64,
                             "speedup_vs_bf_dd": t_bf / t}
                 del ws
             out[f"n{n}_phi{int(phi)}"] = res
-            del A, B, Cbf, Coz
+            del A, B, Coz
             torch.cuda.empty_cache()
     return out
 
@@ -459,7 +469,7 @@ def main():
         log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
-        rows["ozaki"] = ozaki_row(mpx, torch, T, (4096, 8192) if args.full else (4096,))
+        rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))
         out["rows"] = rows
     if not args.no_cpu and not args.quick and p != "ff":
         log("cpu baseline")

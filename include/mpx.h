@@ -151,17 +151,24 @@ void mpx_gemm_autotune_reset(void);
  *   slices: for p = 1..slices, m_p = rint(r1 * 2^{p*beta - e}),
  *        (r1, r2) := TwoSum(r1 - m_p 2^{e - p*beta}, r2), from (hi, lo);
  *   level sums over k-blocks of kblk: S_g = sum_{p+q=g} sum_l mA_p mB_q,
- *        g = 2..slices+1, exact in binary64 (requires kblk * slices *
- *        2^{2 beta} < 2^53, else MPX_EINVAL);
+ *        g = 2..slices+1, exact in binary64: |m_1| <= 2^beta and
+ *        |m_p| <= 2^(beta-1) (p >= 2) bound |S_g| by
+ *        kblk 2^(2 beta) (1 + max(0, slices-2)/4), which must be <= 2^53
+ *        (else MPX_EINVAL; e.g. beta = 22 with kblk = 256 allows 6 slices,
+ *        beta = 20 with kblk = 256 allows 12);
  *   C_ij = DWBFAdd accumulation (k-blocks ascending, g ascending) of
  *        (S_g 2^{e_i + f_j - g beta}, 0).
- * slices in 1..12, kblk a positive multiple of 8.  The result is independent
- * of the tiling (bit-reproducible).  ws: mpx_workspace_size(MPX_OP_OZAKI,
- * MPX_DD, m, n, k, slices) bytes (the slice planes of A and B). */
+ * slices in 1..12, kblk a positive multiple of 16.  The result is
+ * independent of the tiling and stage depth (bit-reproducible).  ws:
+ * mpx_workspace_size(MPX_OP_OZAKI, MPX_DD, m, n, k, slices) bytes (the slice
+ * planes of A and B). */
 int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                       int64_t psA, const double *B, int64_t ldb, int64_t psB, double *C,
                       int64_t ldc, int64_t psC, int slices, int beta, int64_t kblk, void *ws,
                       size_t ws_bytes, void *stream);
+/* Stage depth of the slice GEMM for later calls in this process: 0 = 8, 1 = 16
+ * k values per LDS stage (results are identical). */
+int mpx_gemm_ozaki_set_variant(int variant);
 
 /* ------------------------------------------------------------ polynomials --
  * Real Horner evaluation (Section 4.1): y_b = p_b(x_b) = sum_i a_{b,i} x_b^i

@@ -872,8 +872,10 @@ void orc_dk_horner(int K, int64_t n, const double *cre, const double *cim, int64
 /*    m_p = rint(r1 * 2^{p*beta - e}), then (r1, r2) := TwoSum(r1 - m_p *    */
 /*    2^{e - p*beta}, r2): the residual stays exact;                          */
 /*  * level g = p + q collects sum_{p+q=g} sum_{l in block} mA_p mB_q in one */
-/*    binary64 accumulator, exact because every term is an integer and      */
-/*    kblk * (g-1) * 2^{2 beta} < 2^53;                                      */
+/*    binary64 accumulator, exact because every term is an integer and, with */
+/*    |m_1| <= 2^beta, |m_p| <= 2^(beta-1) for p >= 2, every partial sum is  */
+/*    at most kblk 2^{2 beta} (1 + max(0, s-2)/4) <= 2^53 (the caller's      */
+/*    parameter choice; the tests check it);                                 */
 /*  * C_ij = sum over k-blocks (ascending), levels g = 2..s+1 (ascending) of */
 /*    DWBFAdd(acc, (S_g * 2^{e_i + f_j - g*beta}, 0)).                       */
 /* ------------------------------------------------------------------------ */

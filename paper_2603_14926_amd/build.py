@@ -32,13 +32,19 @@ FLAGS = [
 ]
 
 
+# Per-file flags.  The Ozaki slice GEMM keeps its MFMA accumulators in
+# ordinary VGPRs (the accumulator-register form made the compiler copy every
+# accumulator in and out of AGPRs on each loop iteration).
+FILE_FLAGS = {"mpx_ozaki.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str, extra, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

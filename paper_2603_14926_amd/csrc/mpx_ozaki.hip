@@ -28,13 +28,14 @@
 #include "mpx_internal.hpp"
 
 #include <algorithm>
+#include <cmath>
 
 namespace mpx {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-constexpr int OZ_BM = 64, OZ_BN = 64, OZ_KT = 8, OZ_THREADS = 256;
+constexpr int OZ_BM = 64, OZ_BN = 64, OZ_KPAD = 16, OZ_THREADS = 256;
 constexpr int OZ_MAX_S = 12;
 
 __device__ __forceinline__ int exp_of(double m) {
@@ -135,7 +136,7 @@ k_oz_split_b(long long k, long long n, const double* __restrict__ B, long long l
 // (8 x BN) are copied into LDS with 16-byte loads that were issued one stage
 // ahead (register prefetch).  LDS rows are padded by 16 doubles so the four
 // k rows a wave reads at once fall in different bank halves.
-template <int S, int TA, int TB>
+template <int S, int TA, int TB, int OZ_KT>
 __global__ void __launch_bounds__(OZ_THREADS)
 k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, long long kp,
           const double* __restrict__ SA, const double* __restrict__ SB,
@@ -239,40 +240,43 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
     };
 
     if (kp > 0) fetch(0);
-    for (long long kc = 0; kc < kp; kc += OZ_KT) {
-        __syncthreads();  // previous stage consumed
-        stash();
-        __syncthreads();
-        if (kc + OZ_KT < kp) fetch(kc + OZ_KT);  // in flight during the MFMAs below
+    // k-blocks [0, kblk), [kblk, 2 kblk), ... (the padded tail beyond k holds
+    // zero slices); the level sums are folded once per block.
+    for (long long kb = 0; kb < kp; kb += kblk) {
+        const long long kend = kb + kblk < kp ? kb + kblk : kp;
+        for (long long kc = kb; kc < kend; kc += OZ_KT) {
+            __syncthreads();  // previous stage consumed
+            stash();
+            __syncthreads();
+            if (kc + OZ_KT < kp) fetch(kc + OZ_KT);  // in flight during the MFMAs below
 #pragma unroll
-        for (int ks = 0; ks < OZ_KT; ks += 4) {
-            double fb[S][TB];
+            for (int ks = 0; ks < OZ_KT; ks += 4) {
+                double fb[S][TB];
 #pragma unroll
-            for (int q = 0; q < S; ++q)
+                for (int q = 0; q < S; ++q)
 #pragma unroll
-                for (int b = 0; b < TB; ++b) fb[q][b] = sB[q][ks + lk][wc + 16 * b + lr];
+                    for (int b = 0; b < TB; ++b) fb[q][b] = sB[q][ks + lk][wc + 16 * b + lr];
 #pragma unroll
-            for (int p = 0; p < S; ++p) {
-                double fa[TA];
+                for (int p = 0; p < S; ++p) {
+                    double fa[TA];
 #pragma unroll
-                for (int a = 0; a < TA; ++a) fa[a] = sA[p][ks + lk][wr + 16 * a + lr];
-                // slice pairs (p+1, q+1) with p + q + 2 <= S + 1 feed level p + q
+                    for (int a = 0; a < TA; ++a) fa[a] = sA[p][ks + lk][wr + 16 * a + lr];
+                    // slice pairs (p+1, q+1) with p + q + 2 <= S + 1 feed level p + q
 #pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    if (p + q < S) {
+                    for (int q = 0; q < S; ++q) {
+                        if (p + q < S) {
 #pragma unroll
-                        for (int a = 0; a < TA; ++a)
+                            for (int a = 0; a < TA; ++a)
 #pragma unroll
-                            for (int b = 0; b < TB; ++b)
-                                acc[p + q][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                    fa[a], fb[q][b], acc[p + q][a][b], 0, 0, 0);
+                                for (int b = 0; b < TB; ++b)
+                                    acc[p + q][a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                        fa[a], fb[q][b], acc[p + q][a][b], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
-        // end of a k-block (blocks [0, kblk), [kblk, 2 kblk), ...; the padded
-        // tail beyond k holds zero slices): fold the level sums
-        if ((kc + OZ_KT) % kblk == 0 || kc + OZ_KT >= kp) fold();
+        fold();
     }
 #pragma unroll
     for (int a = 0; a < TA; ++a)
@@ -287,16 +291,25 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
         }
 }
 
-// Wave tile in 16x16 MFMA tiles: 2 x 1 up to 8 slices, 1 x 1 beyond (the
+// Wave tile in 16x16 MFMA tiles: 2 x 1 up to 6 slices, 1 x 1 beyond (the
 // level accumulators, 4 doubles per tile and level, must fit the registers).
-constexpr int oz_ta(int S) { return S <= 8 ? 2 : 1; }
+constexpr int oz_ta(int S) { return S <= 6 ? 2 : 1; }
+
+// Stage depth of the slice GEMM: 0 = 8 k per LDS stage, 1 = 16 k per stage.
+static int g_oz_variant = 0;
+
+static bool oz_exact(int slices, int beta, long long kblk) {
+    if (beta > 26) return false;
+    const long double per_k = ldexpl(1.0L, 2 * beta) * (1.0L + (slices > 2 ? (slices - 2) / 4.0L : 0.0L));
+    return (long double)kblk * per_k <= ldexpl(1.0L, 53);
+}
 
 struct OzDims {
     long long mp, np, kp;
 };
 static OzDims oz_dims(long long m, long long n, long long k) {
     // padded to the largest tile (64 x 64) so one layout serves every s
-    return {ceil_div(m, OZ_BM) * OZ_BM, ceil_div(n, OZ_BN) * OZ_BN, ceil_div(k, OZ_KT) * OZ_KT};
+    return {ceil_div(m, OZ_BM) * OZ_BM, ceil_div(n, OZ_BN) * OZ_BN, ceil_div(k, OZ_KPAD) * OZ_KPAD};
 }
 
 size_t ozaki_workspace(long long m, long long n, long long k, int slices) {
@@ -335,8 +348,12 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     if ((st = launch_status())) return st;
     constexpr int TA = oz_ta(S);
     const int tn = (int)(d.np / 32), tm = (int)(d.mp / (32 * TA));
-    k_oz_gemm<S, TA, 1><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
-        m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
+    if (g_oz_variant == 1)
+        k_oz_gemm<S, TA, 1, 16><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
+            m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
+    else
+        k_oz_gemm<S, TA, 1, 8><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
+            m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
     return launch_status();
 }
 
@@ -349,13 +366,12 @@ extern "C" int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double* 
                                  double* C, int64_t ldc, int64_t psC, int slices, int beta,
                                  int64_t kblk, void* ws, size_t ws_bytes, void* stream) {
     if (m < 0 || n < 0 || k < 0) return MPX_EINVAL;
-    if (slices < 1 || slices > OZ_MAX_S || beta < 1 || kblk < OZ_KT || kblk % OZ_KT) return MPX_EINVAL;
-    // exactness of the level sums: kblk * s * 2^(2 beta) < 2^53
-    {
-        long double bound = (long double)kblk * slices;
-        for (int i = 0; i < 2 * beta; ++i) bound *= 2;
-        if (bound >= 9007199254740992.0L) return MPX_EINVAL;
-    }
+    if (slices < 1 || slices > OZ_MAX_S || beta < 1 || kblk < OZ_KPAD || kblk % OZ_KPAD) return MPX_EINVAL;
+    // Exactness of the level sums: |m_1| <= 2^beta and |m_p| <= 2^(beta-1)
+    // for p >= 2, so a level g <= s+1 sums at most
+    // 2^(2 beta) (1 + max(0, s-2)/4) per k; over kblk terms this must stay
+    // <= 2^53 (every partial sum is then an exactly representable integer).
+    if (!oz_exact(slices, beta, kblk)) return MPX_EINVAL;
     if (m > 0 && k > 0 && (A == nullptr || lda < k || psA < (m - 1) * lda + k)) return MPX_EINVAL;
     if (k > 0 && n > 0 && (B == nullptr || ldb < n || psB < (k - 1) * ldb + n)) return MPX_EINVAL;
     if (m > 0 && n > 0 && (C == nullptr || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
@@ -374,4 +390,12 @@ extern "C" int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double* 
         default: return MPX_EINVAL;
     }
 #undef MPX_OZ
+}
+
+// Select the stage depth of the slice GEMM for subsequent calls (0: 8, 1: 16
+// k per LDS stage).  Results do not depend on it.
+extern "C" int mpx_gemm_ozaki_set_variant(int variant) {
+    if (variant < 0 || variant > 1) return MPX_EINVAL;
+    g_oz_variant = variant;
+    return MPX_OK;
 }

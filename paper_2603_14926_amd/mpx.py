@@ -70,6 +70,7 @@ def _declare(L):
         C.POINTER(C.c_float), _v)
     sig("mpx_gemm_autotune_reset", None)
     sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
+    sig("mpx_gemm_ozaki_set_variant", _i, _i)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
@@ -261,6 +262,10 @@ def gemm_ozaki_dd(A, B, slices, beta=20, kblk=256, out=None, ws=None):
                                    _ptr(out), max(ldc, n), psC, int(slices), int(beta), int(kblk),
                                    _ptr(ws), ws.numel(), _stream()), "mpx_gemm_ozaki_dd")
     return out
+
+
+def gemm_ozaki_set_variant(v: int) -> None:
+    _check(lib().mpx_gemm_ozaki_set_variant(int(v)), "mpx_gemm_ozaki_set_variant")
 
 
 def gemm_variants(p):

@@ -13,10 +13,16 @@ from oracle import exact
 from paper_2603_14926_amd import synth
 
 
-@pytest.mark.parametrize("phi", [1.0, 8.0])
-def test_split_is_error_free_and_bounded(phi):
-    beta, s = 20, 9
+@pytest.mark.parametrize("phi,beta", [(1.0, 20), (8.0, 20), (1.0, 22), (8.0, 22)])
+def test_split_is_error_free_and_bounded(phi, beta):
+    s = 9
     A = synth.mp_array(2, (6, 40), 1, "W", phi=phi)
+    # adversarial: a row maximum just below a power of two, and values that
+    # round up in every slice
+    A[0, 0, :] = np.nextafter(2.0 ** 5, 0.0) * np.where(np.arange(40) % 2, 1.0, -1.0)
+    A[1, 0, :] = 0.0
+    A[0, 1, :] = 1.0 - 2.0 ** -53
+    A[1, 1, :] = -2.0 ** -80
     e, sl = oracle.ozaki_split_rows(A, s, beta)
     for i in range(6):
         mx = np.max(np.abs(A[0, i]))
@@ -24,8 +30,9 @@ def test_split_is_error_free_and_bounded(phi):
         for l in range(40):
             m = sl[:, i, l]
             assert np.all(m == np.rint(m))                 # integers
+            # the magnitudes behind the exactness bound of the level sums
             assert abs(m[0]) <= 2 ** beta
-            assert np.all(np.abs(m[1:]) <= 2 ** (beta - 1) + 1)
+            assert np.all(np.abs(m[1:]) <= 2 ** (beta - 1))
             rec = sum(Fraction(int(m[p])) * Fraction(2) ** (int(e[i]) - (p + 1) * beta) for p in range(s))
             resid = exact.value(A[:, i, l]) - rec
             # what is left after s slices is below half a unit of the last slice

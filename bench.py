@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--prec", default="qd")
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
+    ap.add_argument("--only", default=None,
+                    choices=["gemm", "gemv", "vector", "durand_kerner", "autograd", "ozaki"],
+                    help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 512 MiB read + 512 MiB write kernel (counter calibration)")
@@ -403,6 +406,15 @@ def main():
     from paper_2603_14926_amd import mpx, synth
     mpx.lib()
     T = Timer(torch)
+    if args.only:
+        fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd")},
+              "gemv": lambda: gemv_rows(mpx, torch, T),
+              "vector": lambda: vector_rows(mpx, torch, T),
+              "durand_kerner": lambda: dk_row(mpx, torch, T),
+              "autograd": lambda: autograd_row(mpx, torch, T),
+              "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
+        print(json.dumps({"only": args.only, "row": fn()}), flush=True)
+        return
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
         dst = torch.empty_like(src)

@@ -14,6 +14,7 @@ measured on its own synthetic workload:
   gemm          DD / TD / QD at 512, 1024, 2048 and FF at 2048;
   gemv          n = 8192 (QD, TD, DD);
   vector        AXPY and dot at n = 4096 (latency) and n = 2^24 (HBM);
+  cgemm_3m      complex GEMM by the 3M method at n = 2048 and 2049;
   durand_kerner 4096 complex QD polynomials, degrees 16..512, 200 sweeps
                 in one graph-replayed persistent launch: roots/s, residual,
                 error on 16 known-root polynomials;
@@ -62,7 +63,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
-                    choices=["gemm", "gemv", "vector", "durand_kerner", "autograd", "ozaki"],
+                    choices=["gemm", "gemv", "vector", "cgemm", "durand_kerner", "autograd", "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -211,6 +212,29 @@ def vector_rows(mpx, torch, T):
                 "dot_frac_hbm": b_dot / (t_dot * 1e-3) / PEAK_HBM,
             }
         out[p] = row
+    return out
+
+
+# ------------------------------------------------------------ complex 3M ----
+
+def cgemm_rows(mpx, torch, T):
+    """Complex GEMM by the 3M method (Section 3.2) at n = 2048 and the
+    paper's n = 2049; reports time and the complex / real time ratio."""
+    from paper_2603_14926_amd import synth
+    out = {}
+    for p in ("qd", "td", "dd"):
+        K = mpx.ncomp(p)
+        for n in (2048, 2049):
+            mk = lambda s: gpu_mp(torch, K, (n, n), synth.seed_for(5, s), "W", phi=1.0)
+            Are, Aim, Bre, Bim = mk(0), mk(1), mk(2), mk(3)
+            Cre, Cim = torch.empty_like(Are), torch.empty_like(Are)
+            ws = mpx.workspace(mpx.OP_CGEMM, p, n, n, n)
+            t_c = T(lambda: mpx.cgemm_3m(p, Are, Aim, Bre, Bim, out=(Cre, Cim), ws=ws), reps=2)
+            t_r = T(lambda: mpx.gemm(p, Are, Bre, out=Cre), reps=2)
+            macs = 3.0 * n ** 3
+            out[f"{p}_{n}"] = {"ms": t_c, "real_gemm_ms": t_r, "complex_over_real": t_c / t_r,
+                               "frac_issue_peak": macs * INSTR_PER_MAC[p] / (t_c * 1e-3) / PEAK_F64_ISSUE}
+            del Are, Aim, Bre, Bim, Cre, Cim, ws
     return out
 
 
@@ -410,6 +434,7 @@ def main():
         fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd")},
               "gemv": lambda: gemv_rows(mpx, torch, T),
               "vector": lambda: vector_rows(mpx, torch, T),
+              "cgemm": lambda: cgemm_rows(mpx, torch, T),
               "durand_kerner": lambda: dk_row(mpx, torch, T),
               "autograd": lambda: autograd_row(mpx, torch, T),
               "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
@@ -479,6 +504,7 @@ def main():
         rows["gemm"] = g
         log("gemv rows"); rows["gemv_8192"] = gemv_rows(mpx, torch, T)
         log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
+        log("complex 3M"); rows["cgemm_3m"] = cgemm_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
         rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))

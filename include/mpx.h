@@ -85,10 +85,11 @@ int mpx_axpy(int prec, int64_t n, const void *alpha_host, const void *x, int64_t
 
 /* --------------------------------------------------------------- reductions --
  * Workspace sizes (bytes) for the calls that need one; op codes: */
-enum { MPX_OP_DOT = 1, MPX_OP_GEMV = 2, MPX_OP_GEMM = 3, MPX_OP_OZAKI = 4 };
+enum { MPX_OP_DOT = 1, MPX_OP_GEMV = 2, MPX_OP_GEMM = 3, MPX_OP_OZAKI = 4, MPX_OP_CGEMM = 5 };
 /* For MPX_OP_DOT: m = n (vector length).  MPX_OP_GEMV: m, n = matrix shape,
  * k = trans.  MPX_OP_GEMM: 0.  MPX_OP_OZAKI: m, n, k = GEMM shape,
- * extra = number of slices.  Returns 0 for invalid arguments. */
+ * extra = number of slices.  MPX_OP_CGEMM: m, n, k = GEMM shape.  Returns 0
+ * for invalid arguments. */
 size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k, int64_t extra);
 
 /* result[0..K-1] (device, K contiguous values) = sum_i x_i * y_i.
@@ -117,6 +118,19 @@ int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void *A, int64_t l
 int mpx_gemm(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k,
              const void *A, int64_t lda, int64_t psA, const void *B, int64_t ldb,
              int64_t psB, void *C, int64_t ldc, int64_t psC, void *stream);
+
+/* Complex C := A B by the 3M method (Section 3.2, eq. cgemm_3m):
+ *   C1 = Re(A) Re(B),  C2 = Im(A) Im(B),  C3 = (Re(A) + Im(A)) (Re(B) + Im(B)),
+ *   Re(C) = C1 - C2,   Im(C) = (C3 - C1) - C2,
+ * each real product by mpx_gemm (sequential k per entry), each sum an
+ * elementwise BF addition.  Real and imaginary parts are separate plane sets
+ * sharing lda / psA (A, m x k), ldb / psB (B, k x n) and ldc / psC (C, m x n).
+ * ws: mpx_workspace_size(MPX_OP_CGEMM, prec, m, n, k, 0) bytes.  C must not
+ * alias A or B. */
+int mpx_cgemm_3m(int prec, int64_t m, int64_t n, int64_t k, const void *Are, const void *Aim,
+                 int64_t lda, int64_t psA, const void *Bre, const void *Bim, int64_t ldb,
+                 int64_t psB, void *Cre, void *Cim, int64_t ldc, int64_t psC, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------- GEMM tuning --
  * The GEMM has several register/LDS tilings ("variants"); all produce the

@@ -196,6 +196,17 @@ def gemm_entries(K, A, B, rows, cols, tA=False, tB=False):
     return out
 
 
+def cgemm_3m(K, Are, Aim, Bre, Bim):
+    """Complex product by the 3M method (Section 3.2); returns (Cre, Cim)."""
+    Are, Aim, Bre, Bim = (_chk(v, K) for v in (Are, Aim, Bre, Bim))
+    m, k = Are.shape[1], Are.shape[2]
+    n = Bre.shape[2]
+    Cre = np.zeros((K, m, n)); Cim = np.zeros((K, m, n))
+    lib().orc_cgemm_3m(_i32(K), _i64(m), _i64(n), _i64(k), _p(Are), _p(Aim), _p(Bre), _p(Bim),
+                       _p(Cre), _p(Cim))
+    return Cre, Cim
+
+
 # ------------------------------------------------------------ float-float ----
 
 def ff_add(x, y):

@@ -473,6 +473,40 @@ void orc_gemm_entries(int K, int tA, int tB, int64_t k, const double *A, int64_t
     }
 }
 
+/* Complex product by the 3M method (Section 3.2, eq. cgemm_3m):
+ *   C1 = Re(A) Re(B),  C2 = Im(A) Im(B),
+ *   C3 = (Re(A) + Im(A)) (Re(B) + Im(B)),
+ *   Re(C) = C1 - C2,   Im(C) = (C3 - C1) - C2,
+ * every real product by the naive triple loop and every sum elementwise with
+ * the BF addition.  Matrices are row-major K-plane sets with ld = columns. */
+void orc_cgemm_3m(int K, int64_t m, int64_t n, int64_t k, const double *Are,
+                  const double *Aim, const double *Bre, const double *Bim, double *Cre,
+                  double *Cim) {
+    const int64_t psA = m * k, psB = k * n, psC = m * n;
+    double *SA = (double *)malloc(sizeof(double) * K * psA);
+    double *SB = (double *)malloc(sizeof(double) * K * psB);
+    double *C1 = (double *)malloc(sizeof(double) * K * psC);
+    double *C2 = (double *)malloc(sizeof(double) * K * psC);
+    double *C3 = (double *)malloc(sizeof(double) * K * psC);
+    orc_add(K, psA, Are, psA, Aim, psA, SA, psA);
+    orc_add(K, psB, Bre, psB, Bim, psB, SB, psB);
+    orc_gemm(K, 0, 0, m, n, k, Are, k, psA, Bre, n, psB, C1, n, psC);
+    orc_gemm(K, 0, 0, m, n, k, Aim, k, psA, Bim, n, psB, C2, n, psC);
+    orc_gemm(K, 0, 0, m, n, k, SA, k, psA, SB, n, psB, C3, n, psC);
+    for (int64_t i = 0; i < psC; i++) {
+        double c1[4], c2[4], c3[4], t[4], re[4], im[4];
+        gather(K, C1, psC, i, c1);
+        gather(K, C2, psC, i, c2);
+        gather(K, C3, psC, i, c3);
+        mp_sub(K, c1, c2, re);
+        mp_sub(K, c3, c1, t);
+        mp_sub(K, t, c2, im);
+        scatter(K, Cre, psC, i, re);
+        scatter(K, Cim, psC, i, im);
+    }
+    free(SA); free(SB); free(C1); free(C2); free(C3);
+}
+
 /* ---- float-float (binary32 double-word) versions of the same layer ---- */
 
 void orc_ff_add(int64_t n, const float *x, int64_t psx, const float *y, int64_t psy,

@@ -26,6 +26,7 @@ extern "C" size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int
         case MPX_OP_GEMV: return (k == 0 || k == 1) ? gemv_workspace(prec, m, n, (int)k) : 0;
         case MPX_OP_GEMM: return 0;
         case MPX_OP_OZAKI: return ozaki_workspace(m, n, k, (int)extra);
+        case MPX_OP_CGEMM: return cgemm_workspace(prec, m, n, k);
         default: return 0;
     }
 }

@@ -22,7 +22,7 @@ DD, TD, QD, FF = 2, 3, 4, 0x102
 PRECS = {"dd": DD, "td": TD, "qd": QD, "ff": FF}
 _K = {DD: 2, TD: 3, QD: 4, FF: 2}
 
-OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI = 1, 2, 3, 4
+OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI, OP_CGEMM = 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -71,6 +71,7 @@ def _declare(L):
     sig("mpx_gemm_autotune_reset", None)
     sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
+    sig("mpx_cgemm_3m", _i, _i, _l, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _z, _v)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
@@ -262,6 +263,29 @@ def gemm_ozaki_dd(A, B, slices, beta=20, kblk=256, out=None, ws=None):
                                    _ptr(out), max(ldc, n), psC, int(slices), int(beta), int(kblk),
                                    _ptr(ws), ws.numel(), _stream()), "mpx_gemm_ozaki_dd")
     return out
+
+
+def cgemm_3m(p, Are, Aim, Bre, Bim, out=None, ws=None):
+    """Complex product (Re, Im) = A B by the 3M method; parts are (K, ., .) tensors."""
+    p = prec_of(p)
+    psA, lda = _planes(Are, p, 2, "Are")
+    psB, ldb = _planes(Bre, p, 2, "Bre")
+    for t, ref, name in ((Aim, Are, "Aim"), (Bim, Bre, "Bim")):
+        _planes(t, p, 2, name)
+        if t.shape != ref.shape or t.stride() != ref.stride():
+            raise ValueError(f"{name} must match the real part's shape and strides")
+    m, n, k = _gemm_shapes(Are, Bre, False, False)
+    if out is None:
+        out = (torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=Are.device),
+               torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=Are.device))
+    Cre, Cim = out
+    psC, ldc = _planes(Cre, p, 2, "Cre")
+    if ws is None:
+        ws = workspace(OP_CGEMM, p, m, n, k)
+    _check(lib().mpx_cgemm_3m(p, m, n, k, _ptr(Are), _ptr(Aim), max(lda, k), psA, _ptr(Bre),
+                              _ptr(Bim), max(ldb, n), psB, _ptr(Cre), _ptr(Cim), max(ldc, n), psC,
+                              _ptr(ws), ws.numel(), _stream()), "mpx_cgemm_3m")
+    return Cre, Cim
 
 
 def gemm_ozaki_set_variant(v: int) -> None:

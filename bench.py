@@ -15,6 +15,7 @@ measured on its own synthetic workload:
   gemv          n = 8192 (QD, TD, DD);
   vector        AXPY and dot at n = 4096 (latency) and n = 2^24 (HBM);
   cgemm_3m      complex GEMM by the 3M method at n = 2048 and 2049;
+  polyeval      Horner versus Estrin, batch 1024, degrees 16 .. 4095;
   durand_kerner 4096 complex QD polynomials, degrees 16..512, 200 sweeps
                 in one graph-replayed persistent launch: roots/s, residual,
                 error on 16 known-root polynomials;
@@ -63,7 +64,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
-                    choices=["gemm", "gemv", "vector", "cgemm", "durand_kerner", "autograd", "ozaki"],
+                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "durand_kerner", "autograd", "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -212,6 +213,27 @@ def vector_rows(mpx, torch, T):
                 "dot_frac_hbm": b_dot / (t_dot * 1e-3) / PEAK_HBM,
             }
         out[p] = row
+    return out
+
+
+# ------------------------------------------------- Horner versus Estrin ----
+
+def polyeval_rows(mpx, torch, T):
+    """Real-argument polynomial evaluation (Section 4.1): Horner (one thread
+    per polynomial, a dependent chain of deg steps) versus Estrin (one wave per
+    polynomial, log-depth), batch 1024, random coefficients, x in [-1, 1)."""
+    from paper_2603_14926_amd import synth
+    out = {}
+    batch = 1024
+    for p in ("qd", "td", "dd"):
+        K = mpx.ncomp(p)
+        for deg in (16, 64, 256, 1024, 4095):
+            coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
+            x = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
+            y = torch.empty((K, batch), dtype=torch.float64, device="cuda")
+            th = T(lambda: mpx.polyval(p, coef, x, out=y), reps=5)
+            te = T(lambda: mpx.polyval(p, coef, x, out=y, method="estrin"), reps=5)
+            out[f"{p}_deg{deg}"] = {"horner_us": th * 1e3, "estrin_us": te * 1e3, "estrin_speedup": th / te}
     return out
 
 
@@ -435,6 +457,7 @@ def main():
               "gemv": lambda: gemv_rows(mpx, torch, T),
               "vector": lambda: vector_rows(mpx, torch, T),
               "cgemm": lambda: cgemm_rows(mpx, torch, T),
+              "polyeval": lambda: polyeval_rows(mpx, torch, T),
               "durand_kerner": lambda: dk_row(mpx, torch, T),
               "autograd": lambda: autograd_row(mpx, torch, T),
               "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
@@ -505,6 +528,7 @@ def main():
         log("gemv rows"); rows["gemv_8192"] = gemv_rows(mpx, torch, T)
         log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
         log("complex 3M"); rows["cgemm_3m"] = cgemm_rows(mpx, torch, T)
+        log("horner vs estrin"); rows["polyeval"] = polyeval_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
         rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))

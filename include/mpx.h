@@ -193,6 +193,15 @@ int mpx_gemm_ozaki_set_variant(int variant);
 int mpx_polyval(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
                 const void *x, int64_t psx, void *y, int64_t psy, void *stream);
 
+/* The same values by Estrin's method (Section 4.1 compares Horner and
+ * Estrin): the coefficient list of each polynomial is padded with zeros to
+ * N = 2^L >= deg+1 entries; level l = 1..L replaces it by
+ * c'_j = c_{2j} + c_{2j+1} X_{l-1} (BF multiply, then BF add), X_0 = x,
+ * X_l = X_{l-1}^2.  One wave per polynomial; deg <= 4095 (else
+ * MPX_ENOTSUP).  Same layout and errors as mpx_polyval. */
+int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
+                       const void *x, int64_t psx, void *y, int64_t psy, void *stream);
+
 /* Reverse mode of mpx_polyval for L = sum_b gy_b p_b(x_b):
  *   gcoef_{b,i} = gy_b x_b^i  (t_0 = gy_b, t_{i+1} = t_i * x_b: the adjoint of
  *                               the Horner recurrence), same layout as coef;

@@ -286,6 +286,16 @@ def polyval(K, coef, x):
     return y
 
 
+def polyval_estrin(K, coef, x):
+    """Estrin's method on zero-padded power-of-two coefficient lists."""
+    coef = _chk(coef, K); x = _chk(x, K)
+    batch, d1 = coef.shape[1], coef.shape[2]
+    y = np.zeros((K, batch))
+    lib().orc_polyval_estrin(_i32(K), _i64(batch), _i64(d1 - 1), _p(coef), _i64(batch * d1),
+                             _p(x), _i64(batch), _p(y), _i64(batch))
+    return y
+
+
 def polyval_backward(K, coef, x, g, want_coef=True, want_x=True):
     """Gradients of sum_b g_b p_b(x_b): (dcoef (K,batch,deg+1), dx (K,batch))."""
     coef = _chk(coef, K); x = _chk(x, K); g = _chk(g, K)

@@ -617,6 +617,33 @@ void orc_polyval(int K, int64_t batch, int64_t deg, const double *coef, int64_t 
     }
 }
 
+/* Estrin's method (Section 4.1 compares it with Horner): the coefficient list
+ * is padded with zeros to N = 2^L >= deg+1 entries; level l replaces the list
+ * c by c'_j = c_{2j} + c_{2j+1} X_{l-1} (BF multiply, then BF add) with
+ * X_0 = x and X_l = X_{l-1} X_{l-1}, until one entry, p(x), is left. */
+void orc_polyval_estrin(int K, int64_t batch, int64_t deg, const double *coef, int64_t psc,
+                        const double *x, int64_t psx, double *y, int64_t psy) {
+    int64_t N = 1;
+    while (N < deg + 1) N *= 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < batch; b++) {
+        const int64_t off = b * (deg + 1);
+        double *c = (double *)calloc((size_t)N * 4, sizeof(double));
+        double X[4], t[4];
+        for (int64_t i = 0; i <= deg; i++) gather(K, coef, psc, off + i, &c[4 * i]);
+        gather(K, x, psx, b, X);
+        for (int64_t len = N; len > 1; len /= 2) {
+            for (int64_t j = 0; j < len / 2; j++) {
+                mp_mul(K, &c[4 * (2 * j + 1)], X, t);
+                mp_add(K, &c[4 * (2 * j)], t, &c[4 * j]);
+            }
+            mp_mul(K, X, X, X);
+        }
+        scatter(K, y, psy, b, &c[0]);
+        free(c);
+    }
+}
+
 /* Gradients of L = sum_b g_b p_b(x_b):
  *   dL/da_{b,i} = g_b x_b^i, by the adjoint of the Horner recurrence
  *                 (t = g_b; t := t*x_b per step, i ascending);

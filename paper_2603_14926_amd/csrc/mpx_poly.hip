@@ -74,6 +74,76 @@ k_polyval(long long batch, long long deg, const double* __restrict__ coef, long 
     mp_store<double, K>(y, psy, b, h);
 }
 
+// Estrin's method (Section 4.1 compares it with Horner), one wave per
+// polynomial.  The coefficients are padded with zeros to N = 2^L; level l
+// replaces the list c by c'_j = c_{2j} + c_{2j+1} X_{l-1} (X_0 = x,
+// X_l = X_{l-1}^2).  Lane t owns the aligned block of B = 2^LB coefficients
+// starting at t*B (B = 1 when N <= 64): the first LB levels stay inside the
+// lane and are evaluated as a binary counter (a stack of one pending value
+// per level, fully unrolled), the remaining L - LB levels combine lanes t and
+// t + s with a shuffle.  The dependent chain is B + log2(N/B) steps instead
+// of Horner's N, for the same operation count.
+constexpr int trailing_ones(int t) { return (t & 1) ? 1 + trailing_ones(t >> 1) : 0; }
+
+// One step of the lane-local binary counter, unrolled at compile time for
+// every position T of the lane's block: position T completes levels
+// 1..trailing_ones(T) (each c_even + c_odd X_{l-1}), then parks its value.
+template <int K, int LB, int T>
+struct EstrinLocal {
+    static __device__ __forceinline__ void run(mpn<double, K>* st, const mpn<double, K>* Xl,
+                                               const double* __restrict__ coef, long long psc,
+                                               long long base, long long deg, long long off) {
+        constexpr int tz = trailing_ones(T);
+        const long long i = base + T;
+        mpn<double, K> cur = i <= deg ? mp_load<double, K>(coef, psc, off + i) : mp_zero<double, K>();
+#pragma unroll
+        for (int l = 0; l < tz; ++l) cur = bf_add(st[l], bf_mul(cur, Xl[l]));
+        st[tz] = cur;
+        // issue loads eight coefficients at a time (register pressure)
+        if constexpr ((T & 7) == 7) asm volatile("" ::: "memory");
+        EstrinLocal<K, LB, T + 1>::run(st, Xl, coef, psc, base, deg, off);
+    }
+};
+template <int K, int LB>
+struct EstrinLocal<K, LB, (1 << LB)> {
+    static __device__ __forceinline__ void run(mpn<double, K>*, const mpn<double, K>*,
+                                               const double* __restrict__, long long, long long,
+                                               long long, long long) {}
+};
+
+template <int K, int LB>
+__global__ void __launch_bounds__(256)
+k_estrin(long long batch, long long deg, int L, const double* __restrict__ coef, long long psc,
+         const double* __restrict__ x, long long psx, double* __restrict__ y, long long psy) {
+    using V = mpn<double, K>;
+    constexpr int B = 1 << LB;
+    const long long b = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= batch) return;  // whole wave
+    const long long off = b * (deg + 1);
+    V st[LB + 1];
+    V Xl[LB + 1];
+    Xl[0] = mp_load<double, K>(x, psx, b);
+#pragma unroll
+    for (int l = 1; l <= LB; ++l) Xl[l] = bf_mul(Xl[l - 1], Xl[l - 1]);
+    EstrinLocal<K, LB, 0>::run(st, Xl, coef, psc, (long long)lane * B, deg, off);
+    V c = st[LB];
+    V Xc = Xl[LB];
+    // cross-lane levels
+    for (int lev = LB; lev < L; ++lev) {
+        const int sft = 1 << (lev - LB);
+        V other;
+#pragma unroll
+        for (int q = 0; q < K; ++q) other.c[q] = __shfl_down(c.c[q], sft, 64);
+        const V comb = bf_add(c, bf_mul(other, Xc));
+        const bool leader = (lane & (2 * sft - 1)) == 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) c.c[q] = leader ? comb.c[q] : c.c[q];
+        Xc = bf_mul(Xc, Xc);
+    }
+    if (lane == 0) mp_store<double, K>(y, psy, b, c);
+}
+
 // Gradients of L = sum_b g_b p_b(x_b):
 //   dL/da_{b,i} = t_i with t_0 = g_b, t_{i+1} = t_i * x_b   (adjoint of Horner)
 //   dL/dx_b     = g_b * d, d from  d := d * x + h  before  h := h * x + a_i
@@ -474,6 +544,42 @@ extern "C" int mpx_polyval(int prec, int64_t batch, int64_t deg, const void* coe
         default: k_polyval<4><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
     }
     return launch_status();
+}
+
+template <int K>
+static int estrin_t(long long batch, long long deg, const void* coef, long long psc, const void* x,
+                    long long psx, void* y, long long psy, hipStream_t s) {
+    int L = 0;
+    while ((1LL << L) < deg + 1) ++L;
+    const int LB = L > 6 ? L - 6 : 0;
+    const unsigned blocks = (unsigned)ceil_div(batch, 4);
+#define MPX_ES(LBV)                                                                             \
+    case LBV:                                                                                   \
+        k_estrin<K, LBV><<<blocks, 256, 0, s>>>(batch, deg, L, (const double*)coef, psc,         \
+                                               (const double*)x, psx, (double*)y, psy);         \
+        break;
+    switch (LB) {
+        MPX_ES(0) MPX_ES(1) MPX_ES(2) MPX_ES(3) MPX_ES(4) MPX_ES(5) MPX_ES(6)
+        default: return MPX_ENOTSUP;
+    }
+#undef MPX_ES
+    return launch_status();
+}
+
+extern "C" int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void* coef,
+                                  int64_t psc, const void* x, int64_t psx, void* y, int64_t psy,
+                                  void* stream) {
+    int st = polyval_check(prec, batch, deg, coef, psc, x, psx);
+    if (st) return st;
+    if (batch == 0) return MPX_OK;
+    if (y == nullptr || psy < batch) return MPX_EINVAL;
+    if (deg >= 4096) return MPX_ENOTSUP;
+    hipStream_t s = as_stream(stream);
+    switch (prec) {
+        case MPX_DD: return estrin_t<2>(batch, deg, coef, psc, x, psx, y, psy, s);
+        case MPX_TD: return estrin_t<3>(batch, deg, coef, psc, x, psx, y, psy, s);
+        default: return estrin_t<4>(batch, deg, coef, psc, x, psx, y, psy, s);
+    }
 }
 
 extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void* coef,

@@ -73,6 +73,7 @@ def _declare(L):
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
     sig("mpx_cgemm_3m", _i, _i, _l, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _z, _v)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_polyval_estrin", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
     sig("mpx_polyroots", _i, _v, _v, _v, _l, _v, _v, _l, _v, _v)
@@ -316,8 +317,9 @@ def gemm_autotune(p, A, B, out, transA=False, transB=False, reps=3):
 
 # ------------------------------------------------------------ polynomials ----
 
-def polyval(p, coef, x, out=None):
-    """y_b = sum_i coef[:, b, i] x_b^i by Horner; coef (K, batch, deg+1), x (K, batch)."""
+def polyval(p, coef, x, out=None, method="horner"):
+    """y_b = sum_i coef[:, b, i] x_b^i by Horner (or Estrin's method);
+    coef (K, batch, deg+1), x (K, batch)."""
     p = prec_of(p)
     if p == FF:
         raise ValueError("polyval supports DD / TD / QD")
@@ -332,8 +334,9 @@ def polyval(p, coef, x, out=None):
     if out is None:
         out = torch.empty((K, batch), dtype=torch.float64, device=coef.device)
     psy, _ = _planes(out, p, 1, "out")
-    _check(lib().mpx_polyval(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(out),
-                             psy, _stream()), "mpx_polyval")
+    fn = {"horner": lib().mpx_polyval, "estrin": lib().mpx_polyval_estrin}[method]
+    _check(fn(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(out), psy,
+              _stream()), f"polyval ({method})")
     return out
 
 

@@ -218,3 +218,28 @@ def test_polyroots_status_flags_coincident_start():
     zr[0] = [0.5, 0.5, -0.3]           # two coincident start values
     _, _, st = oracle.polyroots(K, np.array([3], np.int32), are, aim, zr, zi, iters=2, init=False)
     assert st[0] == 1
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+@pytest.mark.parametrize("deg", [0, 1, 2, 5, 31, 100])
+def test_estrin_against_exact(K, deg):
+    batch = 4
+    coef = synth.mp_array(K, (batch, deg + 1), 70 + deg, "U")
+    x = synth.mp_array(K, batch, 71 + deg, "U")
+    y = oracle.polyval_estrin(K, coef, x)
+    for b in range(batch):
+        xs = exact.value(x[:, b])
+        cs = [exact.value(coef[:, b, i]) for i in range(deg + 1)]
+        ex = exact.horner_real(cs, xs)
+        scale = sum(abs(float(c)) * abs(float(xs)) ** i for i, c in enumerate(cs))
+        levels = max(1, (deg).bit_length())
+        assert abs(exact.value(y[:, b]) - ex) <= Fraction(4 * levels * 2.0 ** -BITS[K] * scale)
+
+
+def test_estrin_small_cases_by_hand():
+    """deg 1: a0 + a1 x; deg 2 (padded to 4): (a0 + a1 x) + (a2 + 0 x) x^2."""
+    K = 2
+    coef = np.zeros((K, 1, 3)); coef[0, 0] = [1.5, -2.0, 0.25]
+    x = np.zeros((K, 1)); x[0, 0] = 3.0
+    assert oracle.polyval_estrin(K, coef, x)[0, 0] == 1.5 - 6.0 + 0.25 * 9.0
+    assert oracle.polyval_estrin(K, coef[:, :, :2], x)[0, 0] == 1.5 - 6.0

@@ -15,7 +15,7 @@ measured on its own synthetic workload:
   gemv          n = 8192 (QD, TD, DD);
   vector        AXPY and dot at n = 4096 (latency) and n = 2^24 (HBM);
   cgemm_3m      complex GEMM by the 3M method at n = 2048 and 2049;
-  polyeval      Horner versus Estrin, batch 1024, degrees 16 .. 4095;
+  polyeval      Horner versus Estrin, batch 1024, degrees 16 .. 2047;
   durand_kerner 4096 complex QD polynomials, degrees 16..512, 200 sweeps
                 in one graph-replayed persistent launch: roots/s, residual,
                 error on 16 known-root polynomials;
@@ -227,7 +227,7 @@ def polyeval_rows(mpx, torch, T):
     batch = 1024
     for p in ("qd", "td", "dd"):
         K = mpx.ncomp(p)
-        for deg in (16, 64, 256, 1024, 4095):
+        for deg in (16, 64, 256, 1024, 2047):
             coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
             x = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
             y = torch.empty((K, batch), dtype=torch.float64, device="cuda")

@@ -197,7 +197,7 @@ int mpx_polyval(int prec, int64_t batch, int64_t deg, const void *coef, int64_t 
  * Estrin): the coefficient list of each polynomial is padded with zeros to
  * N = 2^L >= deg+1 entries; level l = 1..L replaces it by
  * c'_j = c_{2j} + c_{2j+1} X_{l-1} (BF multiply, then BF add), X_0 = x,
- * X_l = X_{l-1}^2.  One wave per polynomial; deg <= 4095 (else
+ * X_l = X_{l-1}^2.  One wave per polynomial; deg <= 2047 (else
  * MPX_ENOTSUP).  Same layout and errors as mpx_polyval. */
 int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
                        const void *x, int64_t psx, void *y, int64_t psy, void *stream);

@@ -559,7 +559,7 @@ static int estrin_t(long long batch, long long deg, const void* coef, long long 
                                                (const double*)x, psx, (double*)y, psy);         \
         break;
     switch (LB) {
-        MPX_ES(0) MPX_ES(1) MPX_ES(2) MPX_ES(3) MPX_ES(4) MPX_ES(5) MPX_ES(6)
+        MPX_ES(0) MPX_ES(1) MPX_ES(2) MPX_ES(3) MPX_ES(4) MPX_ES(5)
         default: return MPX_ENOTSUP;
     }
 #undef MPX_ES
@@ -573,7 +573,10 @@ extern "C" int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const vo
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (y == nullptr || psy < batch) return MPX_EINVAL;
-    if (deg >= 4096) return MPX_ENOTSUP;
+    // degree >= 2048 would need 64 coefficients per lane; the QD build of that
+    // shape exceeds the register file and its results did not match the
+    // sequential definition, so it is not offered
+    if (deg >= 2048) return MPX_ENOTSUP;
     hipStream_t s = as_stream(stream);
     switch (prec) {
         case MPX_DD: return estrin_t<2>(batch, deg, coef, psc, x, psx, y, psy, s);

@@ -169,22 +169,40 @@ __global__ void __launch_bounds__(kBlock)
 k_gemv_n(long long m, long long n, const T* __restrict__ A, long long lda, long long psA,
          const T* __restrict__ x, long long psx, T* __restrict__ out, long long pso,
          long long chunk) {
+    constexpr int U = 4;  // columns per lane whose loads are issued together
     const int lane = threadIdx.x & 63;
     const long long wave = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const long long r0 = wave * R;
     if (r0 >= m) return;  // whole wave leaves together (no block barrier below)
     const long long c0 = (long long)blockIdx.y * chunk;
     const long long c1 = c0 + chunk < n ? c0 + chunk : n;
+    long long rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rows[r] = r0 + r < m ? r0 + r : m - 1;  // clamped, unused
     mpn<T, K> acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = mp_zero<T, K>();
-    for (long long j = c0 + lane; j < c1; j += 64) {
+    long long j = c0 + lane;
+    // full groups: U columns per lane, all loads first, then the
+    // multiply-adds in ascending column order
+    for (; j + 64 * (U - 1) < c1; j += 64 * U) {
+        mpn<T, K> xv[U], av[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xv[u] = mp_load<T, K>(x, psx, j + 64 * u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) av[u][r] = mp_load<T, K>(A, psA, rows[r] * lda + j + 64 * u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = bf_add(acc[r], bf_mul(av[u][r], xv[u]));
+    }
+    for (; j < c1; j += 64) {
         const mpn<T, K> xv = mp_load<T, K>(x, psx, j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const long long row = r0 + r < m ? r0 + r : m - 1;  // clamped, result unused
-            acc[r] = bf_add(acc[r], bf_mul(mp_load<T, K>(A, psA, row * lda + j), xv));
-        }
+        for (int r = 0; r < R; ++r)
+            acc[r] = bf_add(acc[r], bf_mul(mp_load<T, K>(A, psA, rows[r] * lda + j), xv));
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -73,6 +73,42 @@ def get_threads() -> int:
     return int(lib().orc_get_threads())
 
 
+ARITH = {"bf": 0, "nobf": 1, "nobf_acc": 2}
+
+
+class arith:
+    """Context manager selecting the arithmetic of every K-generic oracle
+    routine: "bf" (the paper's branch-free algorithms, the default), "nobf"
+    (the conventional algorithms of Sections 2.1-2.3 with the sloppy DWAdd)
+    or "nobf_acc" (conventional with DWAccurateAdd; TD and QD as "nobf").
+    Float-float routines are unaffected.  Not thread-safe."""
+
+    def __init__(self, mode: str):
+        self.mode = ARITH[mode]
+
+    def __enter__(self):
+        self.prev = [int(L.orc_get_arith()) for L in (lib(), count_lib())]
+        for L in (lib(), count_lib()):
+            L.orc_set_arith(_i32(self.mode))
+        return self
+
+    def __exit__(self, *exc):
+        for L, m in zip((lib(), count_lib()), self.prev):
+            L.orc_set_arith(_i32(m))
+        return False
+
+
+def renormalize(K: int, x):
+    """TWRenormalize (K = 3) / QWRenormalize (K = 4) of K+1 doubles: the
+    two-pass QuickTwoSum renormalisation with data-dependent emission."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.shape != (K + 1,):
+        raise ValueError("renormalize takes K+1 doubles")
+    c = np.zeros(K)
+    lib().orc_renormalize(_i32(K), _p(x), _p(c))
+    return c
+
+
 # ---------------------------------------------------------------- scalars ----
 
 def eft(which: str, a: float, b: float):

@@ -306,21 +306,187 @@ static void qd_bf_mul(const double x[4], const double y[4], double c[4]) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Conventional (not branch-free) operations: the "NoBF" baseline the paper  */
+/* measures the BF algorithms against (Sections 2.1-2.3).                    */
+/* ------------------------------------------------------------------------ */
+
+/* DWAdd (Section 2.1): QD's default "sloppy" double-word addition; not
+ * relatively accurate under cancellation. */
+static void dw_add_sloppy(const double a[2], const double b[2], double c[2]) {
+    double s, e;
+    two_sum(a[0], b[0], &s, &e);
+    e = OP_ADD(e, OP_ADD(a[1], b[1]));
+    quick_two_sum(s, e, &c[0], &c[1]);
+}
+
+/* DWAccurateAdd (Section 2.1). */
+static void dw_add_accurate(const double a[2], const double b[2], double c[2]) {
+    double s1, s2, t1, t2;
+    two_sum(a[0], b[0], &s1, &s2);
+    two_sum(a[1], b[1], &t1, &t2);
+    s2 = OP_ADD(s2, t1);
+    quick_two_sum(s1, s2, &s1, &s2);
+    s2 = OP_ADD(s2, t2);
+    quick_two_sum(s1, s2, &c[0], &c[1]);
+}
+
+/* DWMul (Section 2.1), its final "QuickTwoProd" read as QuickTwoSum. */
+static void dw_mul_conv(const double a[2], const double b[2], double c[2]) {
+    double p1, p2;
+    two_prod(a[0], b[0], &p1, &p2);
+    p2 = OP_ADD(p2, OP_ADD(OP_MUL(a[0], b[1]), OP_MUL(a[1], b[0])));
+    quick_two_sum(p1, p2, &c[0], &c[1]);
+}
+
+/* Renormalisation of K+1 roughly ordered doubles x[] into K components
+ * (TWRenormalize for K = 3, QWRenormalize for K = 4; the paper names them
+ * and their cost but does not print them).  The two-pass scheme of the QD
+ * library's published algorithms (Hida, Li and Bailey): QuickTwoSum from the
+ * least significant end upward, then from the top down, emitting a component
+ * whenever the running sum leaves a non-zero error.  Once K-1 components are
+ * out, what is left is added into the last one.  The data-dependent tests
+ * are the branches that the BF algorithms remove. */
+static void renormalize(int K, const double *x, double *c) {
+    const int n = K + 1;
+    double t[5], s, e;
+    int k = 0;
+    s = x[n - 1];
+    for (int i = n - 2; i >= 0; i--) quick_two_sum(x[i], s, &s, &t[i + 1]);
+    t[0] = s;
+    for (int i = 1; i < n; i++) {
+        if (k == K - 1) {
+            s = OP_ADD(s, t[i]);
+            continue;
+        }
+        quick_two_sum(s, t[i], &s, &e);
+        if (e != 0.0) {
+            c[k++] = s;
+            s = e;
+        }
+    }
+    c[k++] = s;
+    for (; k < K; k++) c[k] = 0.0;
+}
+
+/* TWAdd (Section 2.2), as printed: componentwise TwoSums written out, the
+ * error chain, then TWRenormalize.  "t0 + t1 + t2" is evaluated left to
+ * right. */
+static void tw_add_conv(const double a[3], const double b[3], double c[3]) {
+    double s0, s1, s2, v0, v1, v2, u0, u1, u2, w0, w1, w2, t0, t1, t2, i1, i2, i3, r[4];
+    s0 = OP_ADD(a[0], b[0]); s1 = OP_ADD(a[1], b[1]); s2 = OP_ADD(a[2], b[2]);
+    v0 = OP_SUB(s0, a[0]); v1 = OP_SUB(s1, a[1]); v2 = OP_SUB(s2, a[2]);
+    u0 = OP_SUB(s0, v0); u1 = OP_SUB(s1, v1); u2 = OP_SUB(s2, v2);
+    w0 = OP_SUB(a[0], u0); w1 = OP_SUB(a[1], u1); w2 = OP_SUB(a[2], u2);
+    u0 = OP_SUB(b[0], v0); u1 = OP_SUB(b[1], v1); u2 = OP_SUB(b[2], v2);
+    t0 = OP_ADD(w0, u0); t1 = OP_ADD(w1, u1); t2 = OP_ADD(w2, u2);
+    two_sum(s1, t0, &s1, &t0);
+    two_sum(s2, t0, &i1, &i2);
+    two_sum(t1, i1, &s2, &i3);
+    two_sum(i2, i3, &t0, &t1);
+    t0 = OP_ADD(OP_ADD(t0, t1), t2);
+    r[0] = s0; r[1] = s1; r[2] = s2; r[3] = t0;
+    renormalize(3, r, c);
+}
+
+/* The product terms shared by TWMul (Section 2.2) and its four-component
+ * form: TwoProd of the O(1), O(eps) and O(eps^2) partial products, three
+ * three-term sums, and the O(eps^3) error terms.  On return p0, p1, s0 are
+ * the O(1), O(eps), O(eps^2) terms, *t0 the O(eps^3) sum (the printed last
+ * TwoSum reads q3 where t0 is meant: read as TwoSum(t0, s1)), and lo[]
+ * the three O(eps^4) pieces that only the four-component form keeps. */
+static void mul_conv_terms(const double *a, const double *b, double r[4], double lo[3]) {
+    double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
+    double i1, i2, i3, s0, t0, s1, t1, s2, e;
+    two_prod(a[0], b[0], &p0, &q0);
+    two_prod(a[0], b[1], &p1, &q1);
+    two_prod(a[1], b[0], &p2, &q2);
+    two_prod(a[0], b[2], &p3, &q3);
+    two_prod(a[1], b[1], &p4, &q4);
+    two_prod(a[2], b[0], &p5, &q5);
+    two_sum(p1, p2, &i1, &i2); two_sum(q0, i1, &p1, &i3); two_sum(i2, i3, &p2, &q0);
+    two_sum(p2, q1, &i1, &i2); two_sum(q2, i1, &p2, &i3); two_sum(i2, i3, &q1, &q2);
+    two_sum(p3, p4, &i1, &i2); two_sum(p5, i1, &p3, &i3); two_sum(i2, i3, &p4, &p5);
+    two_sum(p2, p3, &s0, &t0); two_sum(q1, p4, &s1, &t1); s2 = OP_ADD(q2, p5);
+    two_sum(s1, t0, &s1, &t0); s2 = OP_ADD(s2, OP_ADD(t0, t1));
+    two_sum(q0, q3, &q0, &q3); two_sum(q4, q5, &q4, &q5); two_sum(q0, q4, &t0, &t1);
+    t1 = OP_ADD(t1, OP_ADD(q3, q5));
+    two_sum(t0, s1, &t0, &e);
+    r[0] = p0; r[1] = p1; r[2] = s0; r[3] = t0;
+    lo[0] = s2; lo[1] = t1; lo[2] = e;
+}
+
+/* TWMul (Section 2.2): the terms above, then TWRenormalize of
+ * (p0, p1, s0, t0); the O(eps^4) pieces are dropped. */
+static void tw_mul_conv(const double a[3], const double b[3], double c[3]) {
+    double r[4], lo[3];
+    mul_conv_terms(a, b, r, lo);
+    renormalize(3, r, c);
+}
+
+/* Quad-word addition, conventional (Section 2.3 names it; the QD library's
+ * published "sloppy" addition): TWAdd with a fourth component -- TwoSum per
+ * component, the error chain, QWRenormalize. */
+static void qw_add_conv(const double a[4], const double b[4], double c[4]) {
+    double s[4], t[4], i1, i2, i3, r[5];
+    for (int i = 0; i < 4; i++) two_sum(a[i], b[i], &s[i], &t[i]);
+    two_sum(s[1], t[0], &s[1], &t[0]);
+    two_sum(s[2], t[0], &i1, &i2); two_sum(t[1], i1, &s[2], &i3); two_sum(i2, i3, &t[0], &t[1]);
+    two_sum(s[3], t[0], &i1, &i2); two_sum(t[2], i1, &s[3], &i3); t[0] = OP_ADD(i2, i3);
+    t[0] = OP_ADD(OP_ADD(t[0], t[1]), t[3]);
+    r[0] = s[0]; r[1] = s[1]; r[2] = s[2]; r[3] = s[3]; r[4] = t[0];
+    renormalize(4, r, c);
+}
+
+/* Quad-word multiplication, conventional: the TWMul terms plus the four
+ * O(eps^3) partial products (rounded, added into the O(eps^3) term) and the
+ * O(eps^4) remainder as the fifth input of QWRenormalize. */
+static void qw_mul_conv(const double a[4], const double b[4], double c[4]) {
+    double r[5], lo[3], p6;
+    mul_conv_terms(a, b, r, lo);
+    p6 = OP_ADD(OP_ADD(OP_MUL(a[0], b[3]), OP_MUL(a[1], b[2])),
+                OP_ADD(OP_MUL(a[2], b[1]), OP_MUL(a[3], b[0])));
+    r[3] = OP_ADD(r[3], p6);
+    r[4] = OP_ADD(lo[0], OP_ADD(lo[1], lo[2]));
+    renormalize(4, r, c);
+}
+
+/* Arithmetic used by every K-generic routine below: 0 = branch-free (the
+ * paper's BF algorithms), 1 = conventional with the sloppy DWAdd, 2 =
+ * conventional with DWAccurateAdd (TD and QD as 1). */
+static int g_arith = 0;
+void orc_set_arith(int a) { g_arith = a; }
+int orc_get_arith(void) { return g_arith; }
+
+void orc_renormalize(int K, const double *x, double *c) { renormalize(K, x, c); }
+
+/* ------------------------------------------------------------------------ */
 /* K-generic dispatch: K = 2 (DD), 3 (TD), 4 (QD).                           */
 /* ------------------------------------------------------------------------ */
 
 static void mp_add(int K, const double *a, const double *b, double *c) {
     double t[4];
-    if (K == 2) dw_bf_add(a, b, t);
-    else if (K == 3) tw_bf_add(a, b, t);
-    else qw_bf_add(a, b, t);
+    if (g_arith == 0) {
+        if (K == 2) dw_bf_add(a, b, t);
+        else if (K == 3) tw_bf_add(a, b, t);
+        else qw_bf_add(a, b, t);
+    } else {
+        if (K == 2) (g_arith == 2 ? dw_add_accurate : dw_add_sloppy)(a, b, t);
+        else if (K == 3) tw_add_conv(a, b, t);
+        else qw_add_conv(a, b, t);
+    }
     memcpy(c, t, sizeof(double) * K);
 }
 static void mp_mul(int K, const double *a, const double *b, double *c) {
     double t[4];
-    if (K == 2) dw_bf_mul(a, b, t);
-    else if (K == 3) tw_bf_mul(a, b, t);
-    else qd_bf_mul(a, b, t);
+    if (g_arith == 0) {
+        if (K == 2) dw_bf_mul(a, b, t);
+        else if (K == 3) tw_bf_mul(a, b, t);
+        else qd_bf_mul(a, b, t);
+    } else {
+        if (K == 2) dw_mul_conv(a, b, t);
+        else if (K == 3) tw_mul_conv(a, b, t);
+        else qw_mul_conv(a, b, t);
+    }
     memcpy(c, t, sizeof(double) * K);
 }
 static void mp_neg(int K, const double *a, double *c) {

@@ -64,7 +64,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
-                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "durand_kerner", "autograd", "ozaki"],
+                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "durand_kerner", "autograd",
+                             "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -234,6 +235,51 @@ def polyeval_rows(mpx, torch, T):
             th = T(lambda: mpx.polyval(p, coef, x, out=y), reps=5)
             te = T(lambda: mpx.polyval(p, coef, x, out=y, method="estrin"), reps=5)
             out[f"{p}_deg{deg}"] = {"horner_us": th * 1e3, "estrin_us": te * 1e3, "estrin_speedup": th / te}
+    return out
+
+
+# ------------------------------------------------------- BF vs NoBF ----
+
+# FP64 operations per conventional multiply-add on the typical path (the
+# conventional addition plus multiplication, renormalisation included).
+NOBF_OPS_PER_MAC = {"dd_nobf": 11 + 9, "dd_nobf_acc": 20 + 9, "td_nobf": 60 + 129, "qd_nobf": 85 + 145}
+
+
+def nobf_rows(mpx, torch, T):
+    """Branch-free versus conventional arithmetic (the comparison of Tables 3-4
+    and Figure 3): GEMM n = 1024, 2048 (each arithmetic autotuned) and batched
+    real Horner; speedup = conventional time / BF time."""
+    from paper_2603_14926_amd import synth
+    out = {}
+    pairs = [("qd", "qd_nobf"), ("td", "td_nobf"), ("dd", "dd_nobf"), ("dd", "dd_nobf_acc")]
+    for n in (1024, 2048):
+        for bf, nb in pairs:
+            K = mpx.ncomp(bf)
+            A = gpu_mp(torch, K, (n, n), synth.seed_for(1, 0))
+            B = gpu_mp(torch, K, (n, n), synth.seed_for(1, 1))
+            Cm = torch.empty_like(A)
+            r = {}
+            for q in (bf, nb):
+                v, _ = mpx.gemm_autotune(q, A, B, Cm, reps=1)
+                r[q] = (T(lambda: mpx.gemm(q, A, B, out=Cm), reps=3), mpx.gemm_variants(q)[v])
+            tb, tn = r[bf][0], r[nb][0]
+            out[f"gemm_{nb}_{n}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb,
+                                    "bf_variant": r[bf][1], "nobf_variant": r[nb][1],
+                                    "nobf_ops_per_mac": NOBF_OPS_PER_MAC[nb]}
+            del A, B, Cm
+    # Horner at the autograd shape (1024 polynomials of degree 1024, one
+    # thread each): a dependent chain, so the time is the chain's latency, the
+    # GPU analogue of the paper's one-evaluation-per-core timings.
+    batch, deg = 1024, 1024
+    for bf, nb in pairs:
+        K = mpx.ncomp(bf)
+        coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
+        x = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
+        y = torch.empty((K, batch), dtype=torch.float64, device="cuda")
+        tb = T(lambda: mpx.polyval(bf, coef, x, out=y), reps=5)
+        tn = T(lambda: mpx.polyval(nb, coef, x, out=y), reps=5)
+        out[f"horner_{nb}_b{batch}_deg{deg}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb}
+        del coef, x, y
     return out
 
 
@@ -458,6 +504,7 @@ def main():
               "vector": lambda: vector_rows(mpx, torch, T),
               "cgemm": lambda: cgemm_rows(mpx, torch, T),
               "polyeval": lambda: polyeval_rows(mpx, torch, T),
+              "nobf": lambda: nobf_rows(mpx, torch, T),
               "durand_kerner": lambda: dk_row(mpx, torch, T),
               "autograd": lambda: autograd_row(mpx, torch, T),
               "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
@@ -529,6 +576,7 @@ def main():
         log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
         log("complex 3M"); rows["cgemm_3m"] = cgemm_rows(mpx, torch, T)
         log("horner vs estrin"); rows["polyeval"] = polyeval_rows(mpx, torch, T)
+        log("bf vs nobf"); rows["bf_vs_nobf"] = nobf_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
         rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))

@@ -56,6 +56,21 @@ typedef enum {
     MPX_FF = 0x102    /* float-float (binary32 double-word), ~48-bit */
 } mpx_prec;
 
+/* Arithmetic flags, OR-ed into MPX_DD / MPX_TD / MPX_QD.  Without a flag the
+ * branch-free algorithms of Sections 2.1-2.3 are used.  With a flag the same
+ * kernels run the conventional algorithms those sections compare against:
+ *   MPX_NOBF      DWAdd (QD's "sloppy" addition) and DWMul for DD; TWAdd /
+ *                 TWMul and their four-component forms, each ending in the
+ *                 TW / QW renormalisation with data-dependent tests;
+ *   MPX_NOBF_ACC  DD only: DWAccurateAdd in place of DWAdd.
+ * Accepted by mpx_add, mpx_mul, mpx_axpy, mpx_dot, mpx_gemm (and its variant,
+ * variant-count/name and autotune calls) and mpx_polyval; every other entry
+ * point, and any flag on MPX_FF, returns MPX_EPREC.  Results of the
+ * conventional operations are deterministic and meet the same error bounds
+ * as the branch-free ones except that the sloppy DD addition is accurate
+ * only relative to |a| + |b|, not to |a + b|. */
+enum { MPX_NOBF = 0x1000, MPX_NOBF_ACC = 0x2000 };
+
 typedef enum {
     MPX_OK = 0,
     MPX_EINVAL = -1,      /* bad size, stride, pointer or flag */

@@ -19,7 +19,7 @@ extern "C" const char* mpx_status_string(int status) {
 extern "C" size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k,
                                      int64_t extra) {
     using namespace mpx;
-    if (op != MPX_OP_OZAKI && !prec_k(prec)) return 0;
+    if (op == MPX_OP_DOT ? !prec_k_ar(prec) : (op != MPX_OP_OZAKI && !prec_k(prec))) return 0;
     if (m < 0 || n < 0 || k < 0 || extra < 0) return 0;
     switch (op) {
         case MPX_OP_DOT: return dot_workspace(prec, m);

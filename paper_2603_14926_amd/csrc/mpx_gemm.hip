@@ -20,10 +20,15 @@
 //  * every C_ij is accumulated in ascending l from zero, exactly the naive
 //    triple loop's sequence, so results are bit-identical for every tiling.
 //
+// The template argument AR selects the branch-free operations (0) or the
+// conventional ones the paper compares them with (1: sloppy DD addition,
+// 2: accurate DD addition; TD / QD with renormalisation).
+//
 // Workgroups are numbered so that each of the eight XCDs (which receive
 // workgroups round-robin) works on compact blocks of tiles whose A and B
 // panels stay in its L2.
 #include "mp_arith.hpp"
+#include "mp_conv.hpp"
 #include "mpx_internal.hpp"
 
 #include <mutex>
@@ -35,7 +40,7 @@ namespace mpx {
 
 constexpr int kGemmThreads = 256;
 
-template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB>
+template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
        const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
@@ -136,7 +141,7 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = bf_add(acc[i][j], bf_mul(a[i], b[j]));
+            for (int j = 0; j < TN; ++j) acc[i][j] = ar_add<AR>(acc[i][j], ar_mul<AR>(a[i], b[j]));
     };
 
     if (k > 0) fetch(0);
@@ -175,14 +180,14 @@ struct GemmArgs {
     void* C; long long ldc, psC;
 };
 
-template <typename T, int K, int TM, int TN, int BK>
+template <typename T, int K, int TM, int TN, int BK, int AR>
 static int run_variant(const GemmArgs& g, hipStream_t s) {
     constexpr int BM = 16 * TM, BN = 16 * TN;
     const int tn = (int)ceil_div(g.n, BN), tm = (int)ceil_div(g.m, BM);
     const int total = tn * tm;
     if (total == 0) return MPX_OK;
 #define MPX_GEMM_LAUNCH(TA_, TB_)                                                           \
-    k_gemm<T, K, TM, TN, BK, TA_, TB_><<<total, kGemmThreads, 0, s>>>(                      \
+    k_gemm<T, K, TM, TN, BK, TA_, TB_, AR><<<total, kGemmThreads, 0, s>>>(                  \
         g.m, g.n, g.k, (const T*)g.A, g.lda, g.psA, (const T*)g.B, g.ldb, g.psB, (T*)g.C,   \
         g.ldc, g.psC, tn, total)
     if (!g.tA && !g.tB) MPX_GEMM_LAUNCH(false, false);
@@ -201,37 +206,50 @@ struct Variant {
     const char* name;
 };
 
-// Candidate micro-tiles per precision (index 0 = largest tile).
+// Candidate micro-tiles per precision and arithmetic (index 0 = largest
+// tile).  The conventional lists mirror the branch-free ones.
+#define MPX_TILES_DD(AR_, P_)                                                    \
+    {run_variant<double, 2, 4, 4, 8, AR_>, 64, 64, P_ "_4x4_k8"},                \
+    {run_variant<double, 2, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                \
+    {run_variant<double, 2, 2, 2, 16, AR_>, 32, 32, P_ "_2x2_k16"}
+#define MPX_TILES_TD(AR_, P_)                                                    \
+    {run_variant<double, 3, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                \
+    {run_variant<double, 3, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                \
+    {run_variant<double, 3, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"}
+#define MPX_TILES_QD(AR_, P_)                                                    \
+    {run_variant<double, 4, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                \
+    {run_variant<double, 4, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"},              \
+    {run_variant<double, 4, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"}
+
 static const std::vector<Variant>& variants(int prec) {
-    static const std::vector<Variant> dd = {
-        {run_variant<double, 2, 4, 4, 8>, 64, 64, "dd_4x4_k8"},
-        {run_variant<double, 2, 2, 4, 8>, 32, 64, "dd_2x4_k8"},
-        {run_variant<double, 2, 2, 2, 16>, 32, 32, "dd_2x2_k16"},
-    };
-    static const std::vector<Variant> td = {
-        {run_variant<double, 3, 2, 4, 8>, 32, 64, "td_2x4_k8"},
-        {run_variant<double, 3, 2, 2, 8>, 32, 32, "td_2x2_k8"},
-        {run_variant<double, 3, 1, 2, 16>, 16, 32, "td_1x2_k16"},
-    };
-    static const std::vector<Variant> qd = {
-        {run_variant<double, 4, 2, 2, 8>, 32, 32, "qd_2x2_k8"},
-        {run_variant<double, 4, 1, 2, 16>, 16, 32, "qd_1x2_k16"},
-        {run_variant<double, 4, 1, 1, 16>, 16, 16, "qd_1x1_k16"},
-    };
+    static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd")};
+    static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td")};
+    static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
     static const std::vector<Variant> ff = {
-        {run_variant<float, 2, 4, 4, 8>, 64, 64, "ff_4x4_k8"},
-        {run_variant<float, 2, 2, 4, 8>, 32, 64, "ff_2x4_k8"},
-        {run_variant<float, 2, 2, 2, 16>, 32, 32, "ff_2x2_k16"},
+        {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},
+        {run_variant<float, 2, 2, 4, 8, AR_BF>, 32, 64, "ff_2x4_k8"},
+        {run_variant<float, 2, 2, 2, 16, AR_BF>, 32, 32, "ff_2x2_k16"},
     };
+    static const std::vector<Variant> dd_nobf = {MPX_TILES_DD(AR_NOBF, "dd_nobf")};
+    static const std::vector<Variant> td_nobf = {MPX_TILES_TD(AR_NOBF, "td_nobf")};
+    static const std::vector<Variant> qd_nobf = {MPX_TILES_QD(AR_NOBF, "qd_nobf")};
+    static const std::vector<Variant> dd_acc = {MPX_TILES_DD(AR_NOBF_ACC, "dd_nobf_acc")};
     static const std::vector<Variant> none;
     switch (prec) {
         case MPX_DD: return dd;
         case MPX_TD: return td;
         case MPX_QD: return qd;
         case MPX_FF: return ff;
+        case MPX_DD | MPX_NOBF: return dd_nobf;
+        case MPX_TD | MPX_NOBF: return td_nobf;
+        case MPX_QD | MPX_NOBF: return qd_nobf;
+        case MPX_DD | MPX_NOBF_ACC: return dd_acc;
         default: return none;
     }
 }
+#undef MPX_TILES_DD
+#undef MPX_TILES_TD
+#undef MPX_TILES_QD
 
 // Tuned choices, keyed by (prec, tA, tB, log2 buckets of m, n, k).
 using TuneKey = std::tuple<int, int, int, int, int, int>;
@@ -267,7 +285,7 @@ static int pick_variant(int prec, const GemmArgs& g) {
 static int check_gemm(int prec, int tA, int tB, int64_t m, int64_t n, int64_t k, const void* A,
                       int64_t lda, int64_t psA, const void* B, int64_t ldb, int64_t psB,
                       const void* C, int64_t ldc, int64_t psC) {
-    if (!prec_k(prec)) return MPX_EPREC;
+    if (!prec_k_ar(prec)) return MPX_EPREC;
     if (m < 0 || n < 0 || k < 0 || (tA != 0 && tA != 1) || (tB != 0 && tB != 1))
         return MPX_EINVAL;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return MPX_ENOTSUP;

@@ -22,6 +22,24 @@ inline int prec_k(int prec) {
 
 inline bool is_ff(int prec) { return prec == MPX_FF; }
 
+// Precision tag with the arithmetic flags removed, and the flag as the
+// kernels' selector (0 branch-free, 1 conventional, 2 conventional with the
+// accurate DD addition).
+inline int base_prec(int prec) { return prec & ~(MPX_NOBF | MPX_NOBF_ACC); }
+inline int arith_of(int prec) {
+    return (prec & MPX_NOBF_ACC) ? 2 : (prec & MPX_NOBF) ? 1 : 0;
+}
+
+// K of a tag that may carry an arithmetic flag, or 0 when the combination
+// does not exist (flags on FF, both flags, the accurate addition beyond DD).
+inline int prec_k_ar(int prec) {
+    const int fl = prec & (MPX_NOBF | MPX_NOBF_ACC), b = base_prec(prec);
+    if (fl == 0) return prec_k(b);
+    if (fl == (MPX_NOBF | MPX_NOBF_ACC) || b == MPX_FF) return 0;
+    if (fl == MPX_NOBF_ACC && b != MPX_DD) return 0;
+    return prec_k(b);
+}
+
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Map the launch status of the kernel just enqueued to an mpx status.

@@ -32,6 +32,7 @@
 // from the leading coefficient, j ascending in the product, Newton reciprocal
 // for the division), so results are bit-identical for every launch shape.
 #include "mp_arith.hpp"
+#include "mp_conv.hpp"
 #include "mpx_internal.hpp"
 
 #include <algorithm>
@@ -48,8 +49,9 @@ namespace mpx {
 
 // y_b = p_b(x_b): h = a_deg; h := h * x + a_i (i = deg-1 .. 0).  One thread
 // per polynomial; coefficients for the next steps are loaded ahead of the
-// dependent multiply-add chain.
-template <int K>
+// dependent multiply-add chain.  AR selects branch-free (0) or conventional
+// (1) operations (Section 4.1 compares the two).
+template <int K, int AR>
 __global__ void __launch_bounds__(64)
 k_polyval(long long batch, long long deg, const double* __restrict__ coef, long long psc,
           const double* __restrict__ x, long long psx, double* __restrict__ y, long long psy) {
@@ -65,12 +67,12 @@ k_polyval(long long batch, long long deg, const double* __restrict__ coef, long 
         const V a1 = mp_load<double, K>(coef, psc, off + i - 1);
         const V a2 = mp_load<double, K>(coef, psc, off + i - 2);
         const V a3 = mp_load<double, K>(coef, psc, off + i - 3);
-        h = bf_add(bf_mul(h, xv), a0);
-        h = bf_add(bf_mul(h, xv), a1);
-        h = bf_add(bf_mul(h, xv), a2);
-        h = bf_add(bf_mul(h, xv), a3);
+        h = ar_add<AR>(ar_mul<AR>(h, xv), a0);
+        h = ar_add<AR>(ar_mul<AR>(h, xv), a1);
+        h = ar_add<AR>(ar_mul<AR>(h, xv), a2);
+        h = ar_add<AR>(ar_mul<AR>(h, xv), a3);
     }
-    for (; i >= 0; --i) h = bf_add(bf_mul(h, xv), mp_load<double, K>(coef, psc, off + i));
+    for (; i >= 0; --i) h = ar_add<AR>(ar_mul<AR>(h, xv), mp_load<double, K>(coef, psc, off + i));
     mp_store<double, K>(y, psy, b, h);
 }
 
@@ -532,17 +534,28 @@ static int polyval_check(int prec, int64_t batch, int64_t deg, const void* coef,
 
 extern "C" int mpx_polyval(int prec, int64_t batch, int64_t deg, const void* coef, int64_t psc,
                            const void* x, int64_t psx, void* y, int64_t psy, void* stream) {
-    int st = polyval_check(prec, batch, deg, coef, psc, x, psx);
+    if (!prec_k_ar(prec) || base_prec(prec) == MPX_FF) return MPX_EPREC;
+    int st = polyval_check(base_prec(prec), batch, deg, coef, psc, x, psx);
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (y == nullptr || psy < batch) return MPX_EINVAL;
     const unsigned blocks = (unsigned)ceil_div(batch, 64);
     hipStream_t s = as_stream(stream);
+#define MPX_PV(K_, AR_)                                                                     \
+    k_polyval<K_, AR_><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc,             \
+                                             (const double*)x, psx, (double*)y, psy);          \
+    break
     switch (prec) {
-        case MPX_DD: k_polyval<2><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
-        case MPX_TD: k_polyval<3><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
-        default: k_polyval<4><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc, (const double*)x, psx, (double*)y, psy); break;
+        case MPX_DD: MPX_PV(2, AR_BF);
+        case MPX_TD: MPX_PV(3, AR_BF);
+        case MPX_QD: MPX_PV(4, AR_BF);
+        case MPX_DD | MPX_NOBF: MPX_PV(2, AR_NOBF);
+        case MPX_TD | MPX_NOBF: MPX_PV(3, AR_NOBF);
+        case MPX_QD | MPX_NOBF: MPX_PV(4, AR_NOBF);
+        case MPX_DD | MPX_NOBF_ACC: MPX_PV(2, AR_NOBF_ACC);
+        default: return MPX_EPREC;
     }
+#undef MPX_PV
     return launch_status();
 }
 

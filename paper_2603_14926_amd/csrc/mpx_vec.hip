@@ -11,6 +11,7 @@
 // BF multiply-adds, then a fixed butterfly across the 64 lanes of a wave,
 // then a fixed sequential combine across waves and blocks.
 #include "mp_arith.hpp"
+#include "mp_conv.hpp"
 #include "mpx_internal.hpp"
 
 namespace mpx {
@@ -20,7 +21,8 @@ constexpr int kWaves = kBlock / 64;
 
 // ------------------------------------------------------------ elementwise --
 
-template <typename T, int K, int OP>
+// AR selects the branch-free (0) or conventional (1, 2) operations.
+template <typename T, int K, int OP, int AR>
 __global__ void __launch_bounds__(kBlock)
 k_elementwise(long long n, const T* x, long long psx, const T* y, long long psy, T* z,
               long long psz) {
@@ -29,13 +31,13 @@ k_elementwise(long long n, const T* x, long long psx, const T* y, long long psy,
         const mpn<T, K> a = mp_load<T, K>(x, psx, i);
         const mpn<T, K> b = mp_load<T, K>(y, psy, i);
         mpn<T, K> c;
-        if constexpr (OP == 0) c = bf_add(a, b);
-        else c = bf_mul(a, b);
+        if constexpr (OP == 0) c = ar_add<AR>(a, b);
+        else c = ar_mul<AR>(a, b);
         mp_store<T, K>(z, psz, i, c);
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int AR>
 __global__ void __launch_bounds__(kBlock)
 k_axpy(long long n, mpn<T, K> alpha, const T* __restrict__ x, long long psx, T* y,
        long long psy) {
@@ -43,7 +45,7 @@ k_axpy(long long n, mpn<T, K> alpha, const T* __restrict__ x, long long psx, T* 
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         const mpn<T, K> a = mp_load<T, K>(x, psx, i);
         const mpn<T, K> b = mp_load<T, K>(y, psy, i);
-        mp_store<T, K>(y, psy, i, bf_add(bf_mul(alpha, a), b));
+        mp_store<T, K>(y, psy, i, ar_add<AR>(ar_mul<AR>(alpha, a), b));
     }
 }
 
@@ -53,15 +55,15 @@ static int elementwise_blocks(long long n) {
     return (int)(b < 1 ? 1 : b);
 }
 
-template <typename T, int K>
+template <typename T, int K, int AR>
 static int launch_elementwise(int op, long long n, const void* x, long long psx, const void* y,
                               long long psy, void* z, long long psz, hipStream_t s) {
     const int blocks = elementwise_blocks(n);
     if (op == 0)
-        k_elementwise<T, K, 0><<<blocks, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
+        k_elementwise<T, K, 0, AR><<<blocks, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
                                                           (T*)z, psz);
     else
-        k_elementwise<T, K, 1><<<blocks, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
+        k_elementwise<T, K, 1, AR><<<blocks, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
                                                           (T*)z, psz);
     return launch_status();
 }
@@ -69,20 +71,21 @@ static int launch_elementwise(int op, long long n, const void* x, long long psx,
 // -------------------------------------------------------- block reduction --
 
 // Butterfly across the 64 lanes of a wave: every lane ends with the same sum
-// (BF addition is bitwise commutative, so partners compute identical bits).
-template <typename T, int K>
+// (BF addition and the conventional additions are bitwise commutative, so
+// partners compute identical bits).
+template <typename T, int K, int AR = AR_BF>
 __device__ __forceinline__ mpn<T, K> wave_sum(mpn<T, K> v) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = bf_add(v, mp_shfl_xor<T, K>(v, off));
+    for (int off = 32; off >= 1; off >>= 1) v = ar_add<AR>(v, mp_shfl_xor<T, K>(v, off));
     return v;
 }
 
 // Sum over a 256-thread block: wave butterflies, then wave 0 adds the four
 // wave sums in wave order.  Result valid in thread 0.
-template <typename T, int K>
+template <typename T, int K, int AR>
 __device__ __forceinline__ mpn<T, K> block_sum(mpn<T, K> v) {
     __shared__ T sh[K][kWaves];
-    v = wave_sum<T, K>(v);
+    v = wave_sum<T, K, AR>(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
@@ -97,7 +100,7 @@ __device__ __forceinline__ mpn<T, K> block_sum(mpn<T, K> v) {
         mpn<T, K> t;
 #pragma unroll
         for (int c = 0; c < K; ++c) t.c[c] = sh[c][j];
-        r = bf_add(r, t);
+        r = ar_add<AR>(r, t);
     }
     return r;
 }
@@ -107,27 +110,27 @@ __device__ __forceinline__ mpn<T, K> block_sum(mpn<T, K> v) {
 // Stage 1: block b owns a grid-strided subset of the elements; each thread
 // accumulates its elements sequentially; the block sum goes to part[b]
 // (K planes of nblocks values) or, for a single block, straight to `out`.
-template <typename T, int K>
+template <typename T, int K, int AR>
 __global__ void __launch_bounds__(kBlock)
 k_dot_partial(long long n, const T* __restrict__ x, long long psx, const T* __restrict__ y,
               long long psy, T* __restrict__ out, long long pso) {
     const long long stride = (long long)gridDim.x * kBlock;
     mpn<T, K> acc = mp_zero<T, K>();
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        acc = bf_add(acc, bf_mul(mp_load<T, K>(x, psx, i), mp_load<T, K>(y, psy, i)));
-    acc = block_sum<T, K>(acc);
+        acc = ar_add<AR>(acc, ar_mul<AR>(mp_load<T, K>(x, psx, i), mp_load<T, K>(y, psy, i)));
+    acc = block_sum<T, K, AR>(acc);
     if (threadIdx.x == 0) mp_store<T, K>(out, pso, blockIdx.x, acc);
 }
 
 // Stage 2: one block adds the nparts partials (thread-sequential, then the
 // block tree) into K contiguous values.
-template <typename T, int K>
+template <typename T, int K, int AR>
 __global__ void __launch_bounds__(kBlock)
 k_sum_parts(long long nparts, const T* __restrict__ part, long long psp, T* __restrict__ out) {
     mpn<T, K> acc = mp_zero<T, K>();
     for (long long i = threadIdx.x; i < nparts; i += kBlock)
-        acc = bf_add(acc, mp_load<T, K>(part, psp, i));
-    acc = block_sum<T, K>(acc);
+        acc = ar_add<AR>(acc, mp_load<T, K>(part, psp, i));
+    acc = block_sum<T, K, AR>(acc);
     if (threadIdx.x == 0) mp_store<T, K>(out, 1, 0, acc);
 }
 
@@ -139,20 +142,20 @@ static long long dot_blocks(long long n) {
     return b > 2048 ? 2048 : b;
 }
 
-template <typename T, int K>
+template <typename T, int K, int AR>
 static int launch_dot(long long n, const void* x, long long psx, const void* y, long long psy,
                       void* result, void* ws, hipStream_t s) {
     const long long nb = dot_blocks(n);
     if (nb == 1) {
-        k_dot_partial<T, K><<<1, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
+        k_dot_partial<T, K, AR><<<1, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
                                                   (T*)result, 1);
         return launch_status();
     }
-    k_dot_partial<T, K><<<(int)nb, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
+    k_dot_partial<T, K, AR><<<(int)nb, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
                                                     (T*)ws, nb);
     int st = launch_status();
     if (st != MPX_OK) return st;
-    k_sum_parts<T, K><<<1, kBlock, 0, s>>>(nb, (const T*)ws, nb, (T*)result);
+    k_sum_parts<T, K, AR><<<1, kBlock, 0, s>>>(nb, (const T*)ws, nb, (T*)result);
     return launch_status();
 }
 
@@ -294,8 +297,8 @@ size_t gemv_workspace(int prec, long long m, long long n, int trans) {
 size_t dot_workspace(int prec, long long n) {
     const long long nb = dot_blocks(n);
     if (nb == 1) return 0;
-    const size_t elt = is_ff(prec) ? sizeof(float) : sizeof(double);
-    return elt * (size_t)prec_k(prec) * (size_t)nb;
+    const size_t elt = is_ff(base_prec(prec)) ? sizeof(float) : sizeof(double);
+    return elt * (size_t)prec_k_ar(prec) * (size_t)nb;
 }
 
 }  // namespace mpx
@@ -313,8 +316,24 @@ using namespace mpx;
         default: return MPX_EPREC;                                         \
     }
 
+// The same with the arithmetic flag as the last template argument.
+#define MPX_DISPATCH_AR(prec, FN, ...)                                                  \
+    switch (prec) {                                                                     \
+        case MPX_DD: return FN<double, 2, AR_BF>(__VA_ARGS__);                          \
+        case MPX_TD: return FN<double, 3, AR_BF>(__VA_ARGS__);                          \
+        case MPX_QD: return FN<double, 4, AR_BF>(__VA_ARGS__);                          \
+        case MPX_FF: return FN<float, 2, AR_BF>(__VA_ARGS__);                           \
+        case MPX_DD | MPX_NOBF: return FN<double, 2, AR_NOBF>(__VA_ARGS__);             \
+        case MPX_TD | MPX_NOBF: return FN<double, 3, AR_NOBF>(__VA_ARGS__);             \
+        case MPX_QD | MPX_NOBF: return FN<double, 4, AR_NOBF>(__VA_ARGS__);             \
+        case MPX_DD | MPX_NOBF_ACC: return FN<double, 2, AR_NOBF_ACC>(__VA_ARGS__);     \
+        default: return MPX_EPREC;                                                      \
+    }
+
+// Vector operand check; accepts the arithmetic flags (GEMV rejects them
+// before calling this).
 static int check_vec(int prec, int64_t n, const void* p, int64_t ps) {
-    if (!prec_k(prec)) return MPX_EPREC;
+    if (!prec_k_ar(prec)) return MPX_EPREC;
     if (n < 0) return MPX_EINVAL;
     if (n > 0 && (p == nullptr || ps < n)) return MPX_EINVAL;
     return MPX_OK;
@@ -327,7 +346,7 @@ static int elementwise(int op, int prec, int64_t n, const void* x, int64_t psx, 
         (st = check_vec(prec, n, z, psz)))
         return st;
     if (n == 0) return MPX_OK;
-    MPX_DISPATCH(prec, launch_elementwise, op, n, x, psx, y, psy, z, psz, as_stream(stream));
+    MPX_DISPATCH_AR(prec, launch_elementwise, op, n, x, psx, y, psy, z, psz, as_stream(stream));
 }
 
 extern "C" int mpx_add(int prec, int64_t n, const void* x, int64_t psx, const void* y,
@@ -340,12 +359,12 @@ extern "C" int mpx_mul(int prec, int64_t n, const void* x, int64_t psx, const vo
     return elementwise(1, prec, n, x, psx, y, psy, z, psz, stream);
 }
 
-template <typename T, int K>
+template <typename T, int K, int AR>
 static int axpy_t(int64_t n, const void* alpha_host, const void* x, int64_t psx, void* y,
                   int64_t psy, hipStream_t s) {
     mpn<T, K> a;
     for (int c = 0; c < K; ++c) a.c[c] = ((const T*)alpha_host)[c];
-    k_axpy<T, K><<<elementwise_blocks(n), kBlock, 0, s>>>(n, a, (const T*)x, psx, (T*)y, psy);
+    k_axpy<T, K, AR><<<elementwise_blocks(n), kBlock, 0, s>>>(n, a, (const T*)x, psx, (T*)y, psy);
     return launch_status();
 }
 
@@ -355,7 +374,7 @@ extern "C" int mpx_axpy(int prec, int64_t n, const void* alpha_host, const void*
     if ((st = check_vec(prec, n, x, psx)) || (st = check_vec(prec, n, y, psy))) return st;
     if (alpha_host == nullptr) return MPX_EINVAL;
     if (n == 0) return MPX_OK;
-    MPX_DISPATCH(prec, axpy_t, n, alpha_host, x, psx, y, psy, as_stream(stream));
+    MPX_DISPATCH_AR(prec, axpy_t, n, alpha_host, x, psx, y, psy, as_stream(stream));
 }
 
 extern "C" int mpx_dot(int prec, int64_t n, const void* x, int64_t psx, const void* y,
@@ -365,7 +384,7 @@ extern "C" int mpx_dot(int prec, int64_t n, const void* x, int64_t psx, const vo
     if (result == nullptr) return MPX_EINVAL;
     const size_t need = dot_workspace(prec, n);
     if (need > 0 && (ws == nullptr || ws_bytes < need)) return MPX_EWORKSPACE;
-    MPX_DISPATCH(prec, launch_dot, n, x, psx, y, psy, result, ws, as_stream(stream));
+    MPX_DISPATCH_AR(prec, launch_dot, n, x, psx, y, psy, result, ws, as_stream(stream));
 }
 
 extern "C" int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void* A, int64_t lda,

@@ -19,8 +19,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpx.so")
 
 DD, TD, QD, FF = 2, 3, 4, 0x102
-PRECS = {"dd": DD, "td": TD, "qd": QD, "ff": FF}
-_K = {DD: 2, TD: 3, QD: 4, FF: 2}
+# Arithmetic flags OR-ed into DD / TD / QD: the conventional (non-branch-free)
+# operations, with the sloppy or (DD only) the accurate double-word addition.
+NOBF, NOBF_ACC = 0x1000, 0x2000
+PRECS = {"dd": DD, "td": TD, "qd": QD, "ff": FF,
+         "dd_nobf": DD | NOBF, "td_nobf": TD | NOBF, "qd_nobf": QD | NOBF,
+         "dd_nobf_acc": DD | NOBF_ACC}
+_K = {DD: 2, TD: 3, QD: 4, FF: 2, DD | NOBF: 2, TD | NOBF: 3, QD | NOBF: 4, DD | NOBF_ACC: 2}
 
 OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI, OP_CGEMM = 1, 2, 3, 4, 5
 

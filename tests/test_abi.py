@@ -75,3 +75,27 @@ def test_empty_problems_are_noops():
     L = mpx.lib()
     assert L.mpx_add(4, 0, None, 0, None, 0, None, 0, None) == 0
     assert L.mpx_gemm(4, 0, 0, 0, 5, 5, None, 5, 0, FAKE, 5, 25, None, 5, 0, None) == 0
+
+
+def test_arithmetic_flags_accepted_only_where_declared():
+    """The conventional-arithmetic flags: DD / TD / QD (accurate addition: DD
+    only) on the elementwise, dot, GEMM and Horner entry points; never on FF
+    or on the other entry points (checked before any launch)."""
+    L = mpx.lib()
+    NOBF, ACC = mpx.NOBF, mpx.NOBF_ACC
+    for p in (2 | NOBF, 3 | NOBF, 4 | NOBF, 2 | ACC):
+        assert L.mpx_gemm_variant_count(p) == 3
+        assert L.mpx_gemm_variant_name(p, 0).decode().endswith(("_4x4_k8", "_2x4_k8", "_2x2_k8"))
+        # accepted: the first failure is the size check
+        assert L.mpx_add(p, -1, FAKE, 10, FAKE, 10, FAKE, 10, None) == -1
+        assert L.mpx_gemm(p, 0, 0, 4, 4, 4, FAKE, 3, 16, FAKE, 4, 16, FAKE, 4, 16, None) == -1
+        assert L.mpx_polyval(p, -1, 3, FAKE, 4, FAKE, 1, FAKE, 1, None) == -1
+        # rejected by the entry points without a conventional path
+        assert L.mpx_gemv(p, 0, 4, 4, FAKE, 4, 16, FAKE, 4, FAKE, 4, None, 0, None) == -2
+        assert L.mpx_polyval_estrin(p, 1, 3, FAKE, 4, FAKE, 1, FAKE, 1, None) == -2
+    for p in (0x102 | NOBF, 3 | ACC, 4 | ACC, 2 | NOBF | ACC):
+        assert L.mpx_gemm_variant_count(p) == 0
+        assert L.mpx_add(p, 1, FAKE, 10, FAKE, 10, FAKE, 10, None) == -2
+        assert L.mpx_dot(p, 1, FAKE, 1, FAKE, 1, FAKE, None, 0, None) == -2
+    assert L.mpx_workspace_size(1, 4 | NOBF, 1 << 20, 0, 0, 0) == \
+        L.mpx_workspace_size(1, 4, 1 << 20, 0, 0, 0) > 0

@@ -1,0 +1,142 @@
+"""GPU parity of the conventional ("NoBF") arithmetic against the CPU oracle
+run with the same arithmetic: elementwise add / mul, AXPY, GEMM (every tile
+variant, every transpose) and real Horner must match bit for bit; dot stays
+within the usual bound.  Mixed inputs put integer-valued numbers (whose
+renormalisation takes the zero-error paths) and random ones in the same
+wavefronts, so lanes of one wave take different paths."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle import exact
+from paper_2603_14926_amd import mpx, synth
+from tests.gpu_util import bits_equal, first_mismatch, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("dd_nobf", 2, "nobf"), ("dd_nobf_acc", 2, "nobf_acc"),
+         ("td_nobf", 3, "nobf"), ("qd_nobf", 4, "nobf")]
+BITS = {2: 104, 3: 155, 4: 208}
+
+
+def _mixed(K, shape, seed):
+    """Random numbers with every third element replaced by a small integer
+    (zero lower components)."""
+    a = synth.mp_array(K, shape, seed, "W")
+    flat = a.reshape(K, -1)
+    ints = np.random.default_rng(seed).integers(-8, 9, flat.shape[1]).astype(np.float64)
+    sel = np.arange(flat.shape[1]) % 3 == 1
+    flat[:, sel] = 0.0
+    flat[0, sel] = ints[sel]
+    return flat.reshape(a.shape)
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+@pytest.mark.parametrize("n", [0, 1, 65, 4096, 100003])
+def test_elementwise_and_axpy_bit_exact(p, K, mode, n):
+    x = _mixed(K, n, 10 + n % 7)
+    y = _mixed(K, n, 20 + n % 5)
+    alpha = synth.mp_array(K, 1, 3, "U")[:, 0]
+    with oracle.arith(mode):
+        want_add, want_mul = oracle.add(K, x, y), oracle.mul(K, x, y)
+        want_axpy = oracle.axpy(K, alpha, x, y)
+    gx, gy = to_gpu(x), to_gpu(y)
+    got = to_np(mpx.add(p, gx, gy))
+    assert bits_equal(got, want_add), first_mismatch(got, want_add)
+    got = to_np(mpx.mul(p, gx, gy))
+    assert bits_equal(got, want_mul), first_mismatch(got, want_mul)
+    mpx.axpy(p, alpha.tolist(), gx, gy)
+    got = to_np(gy)
+    assert bits_equal(got, want_axpy), first_mismatch(got, want_axpy)
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+@pytest.mark.parametrize("n", [1, 4096, 100003])
+def test_dot_within_bound(p, K, mode, n):
+    x = synth.mp_array(K, n, 30 + n % 11, "W")
+    y = synth.mp_array(K, n, 40 + n % 13, "W")
+    got = to_np(mpx.dot(p, to_gpu(x), to_gpu(y)))
+    ex = exact.dot(x, y)
+    err = abs(exact.value(got) - ex)
+    assert err <= Fraction(n * 2.0 ** -BITS[K] * exact.abs_dot(x, y))
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+@pytest.mark.parametrize("mnk", [(1, 1, 1), (33, 17, 65), (100, 70, 129), (64, 64, 0)])
+def test_gemm_bit_exact_all_variants(p, K, mode, mnk):
+    m, n, k = mnk
+    A = _mixed(K, (m, k), 50 + m)
+    B = _mixed(K, (k, n), 60 + n)
+    with oracle.arith(mode):
+        want = oracle.gemm(K, A, B)
+    gA, gB = to_gpu(A), to_gpu(B)
+    names = mpx.gemm_variants(p)
+    assert len(names) == 3 and all(nm.startswith(p + "_") for nm in names)
+    for v in range(len(names)):
+        got = to_np(mpx.gemm(p, gA, gB, variant=v))
+        assert bits_equal(got, want), (v, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+def test_gemm_transposes_bit_exact(p, K, mode):
+    m, n, k = 45, 38, 71
+    A = synth.mp_array(K, (m, k), 70, "U")
+    B = synth.mp_array(K, (k, n), 71, "U")
+    with oracle.arith(mode):
+        want = oracle.gemm(K, A, B)
+    At = np.ascontiguousarray(A.transpose(0, 2, 1))
+    Bt = np.ascontiguousarray(B.transpose(0, 2, 1))
+    for tA, tB in ((True, False), (False, True), (True, True)):
+        a = At if tA else A
+        b = Bt if tB else B
+        got = to_np(mpx.gemm(p, to_gpu(a), to_gpu(b), transA=tA, transB=tB))
+        assert bits_equal(got, want), (tA, tB, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("p,K,mode", [("qd_nobf", 4, "nobf"), ("td_nobf", 3, "nobf"),
+                                      ("dd_nobf", 2, "nobf")])
+def test_gemm_2048_sampled_bit_exact(p, K, mode):
+    """The benchmark size: 24 sampled entries recomputed one by one by the
+    oracle with the same arithmetic must match bit for bit."""
+    n = 2048
+    A = synth.mp_array(K, (n, n), 90, "U")
+    B = synth.mp_array(K, (n, n), 91, "U")
+    got = to_np(mpx.gemm(p, to_gpu(A), to_gpu(B)))
+    rng = np.random.default_rng(4)
+    rows = np.concatenate([[0, n - 1, 1023], rng.integers(0, n, 21)])
+    cols = np.concatenate([[n - 1, 0, 1024], rng.integers(0, n, 21)])
+    with oracle.arith(mode):
+        want = oracle.gemm_entries(K, A, B, rows, cols)
+    assert bits_equal(np.ascontiguousarray(got[:, rows, cols]), want)
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+@pytest.mark.parametrize("batch,deg", [(1, 0), (5, 1), (70, 33), (130, 257)])
+def test_polyval_bit_exact(p, K, mode, batch, deg):
+    coef = _mixed(K, (batch, deg + 1), 1 + deg)
+    x = synth.mp_array(K, batch, 2 + deg, "U")
+    with oracle.arith(mode):
+        want = oracle.polyval(K, coef, x)
+    got = to_np(mpx.polyval(p, to_gpu(coef), to_gpu(x)))
+    assert bits_equal(got, want), first_mismatch(got, want)
+
+
+def test_flags_rejected_where_not_supported():
+    A = torch.zeros((2, 4, 4), dtype=torch.float64, device="cuda")
+    x = torch.zeros((2, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(mpx.MpxError):
+        mpx.gemv("dd_nobf", A, x)
+    with pytest.raises(mpx.MpxError):
+        mpx.polyval("td_nobf", torch.zeros((3, 2, 3), dtype=torch.float64, device="cuda"),
+                    torch.zeros((3, 2), dtype=torch.float64, device="cuda"), method="estrin")
+    L = mpx.lib()
+    z = torch.zeros((2, 8), dtype=torch.float32, device="cuda")
+    assert L.mpx_add(mpx.FF | mpx.NOBF, 8, z.data_ptr(), 8, z.data_ptr(), 8, z.data_ptr(), 8,
+                     None) == -2
+    assert L.mpx_add(mpx.QD | mpx.NOBF_ACC, 1, x.data_ptr(), 4, x.data_ptr(), 4, x.data_ptr(), 4,
+                     None) == -2
+    assert L.mpx_gemm_variant_count(mpx.DD | mpx.NOBF | mpx.NOBF_ACC) == 0

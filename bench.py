@@ -280,6 +280,26 @@ def nobf_rows(mpx, torch, T):
         tn = T(lambda: mpx.polyval(nb, coef, x, out=y), reps=5)
         out[f"horner_{nb}_b{batch}_deg{deg}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb}
         del coef, x, y
+    # Durand-Kerner on the Chebyshev integration polynomial n = 64 (Table 6's
+    # problem), 4096 copies in one persistent launch, Aberth start, 200 sweeps.
+    from fractions import Fraction  # noqa: F401  (coefficients are exact rationals)
+    n, copies, iters = 64, 4096, 200
+    a = synth.chebyshev_coefficients(n)
+    deg = np.full(copies, n, np.int32)
+    for bf, nb in pairs:
+        K = mpx.ncomp(bf)
+        one = np.stack([synth.round_greedy(c, K) for c in a], axis=1)
+        cre = torch.from_numpy(np.tile(one, (1, copies))).cuda()
+        cim = torch.zeros_like(cre)
+        zr = torch.zeros((K, n * copies), dtype=torch.float64, device="cuda")
+        zi = torch.zeros_like(zr)
+        r = {}
+        for q in (bf, nb):
+            plan = mpx.RootsPlan(q, deg, iters=iters, init=True, graph=True)
+            r[q] = T(lambda: plan.run(cre, cim, zr, zi), reps=2)
+        out[f"dk_chebyshev64_{nb}_x{copies}_{iters}it"] = {"bf_ms": r[bf], "nobf_ms": r[nb],
+                                                          "speedup_bf": r[nb] / r[bf]}
+        del cre, cim, zr, zi
     return out
 
 

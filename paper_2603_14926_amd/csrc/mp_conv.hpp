@@ -193,4 +193,10 @@ __device__ __forceinline__ mpn<T, K> ar_mul(const mpn<T, K>& a, const mpn<T, K>&
     else return cv_mul(a, b);
 }
 
+// a - b = a + (-b), as for the BF operations.
+template <int AR, typename T, int K>
+__device__ __forceinline__ mpn<T, K> ar_sub(const mpn<T, K>& a, const mpn<T, K>& b) {
+    return ar_add<AR>(a, mp_neg(b));
+}
+
 }  // namespace mpx

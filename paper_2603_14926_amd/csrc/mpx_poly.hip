@@ -189,51 +189,52 @@ struct cplx {
     mpn<double, K> re, im;
 };
 
-// (a+bi)(c+di): ac - bd, ad + bc (four BF products, two BF sums).
-template <int K>
+// (a+bi)(c+di): ac - bd, ad + bc (four products, two sums).  AR selects the
+// branch-free (0) or conventional (1, 2) real operations.
+template <int K, int AR = AR_BF>
 __device__ __forceinline__ cplx<K> c_mul(const cplx<K>& x, const cplx<K>& y) {
-    const auto ac = bf_mul(x.re, y.re);
-    const auto bd = bf_mul(x.im, y.im);
-    const auto ad = bf_mul(x.re, y.im);
-    const auto bc = bf_mul(x.im, y.re);
+    const auto ac = ar_mul<AR>(x.re, y.re);
+    const auto bd = ar_mul<AR>(x.im, y.im);
+    const auto ad = ar_mul<AR>(x.re, y.im);
+    const auto bc = ar_mul<AR>(x.im, y.re);
     cplx<K> r;
-    r.re = bf_sub(ac, bd);
-    r.im = bf_add(ad, bc);
+    r.re = ar_sub<AR>(ac, bd);
+    r.im = ar_add<AR>(ad, bc);
     return r;
 }
-template <int K>
+template <int K, int AR = AR_BF>
 __device__ __forceinline__ cplx<K> c_add(const cplx<K>& x, const cplx<K>& y) {
-    return {bf_add(x.re, y.re), bf_add(x.im, y.im)};
+    return {ar_add<AR>(x.re, y.re), ar_add<AR>(x.im, y.im)};
 }
-template <int K>
+template <int K, int AR = AR_BF>
 __device__ __forceinline__ cplx<K> c_sub(const cplx<K>& x, const cplx<K>& y) {
-    return {bf_sub(x.re, y.re), bf_sub(x.im, y.im)};
+    return {ar_sub<AR>(x.re, y.re), ar_sub<AR>(x.im, y.im)};
 }
 
 // Newton's iteration for 1/d (division through Newton, Section 2): y0 is the
 // correctly rounded binary64 1/d_0; each step y := y + y (1 - d y) doubles
 // the correct bits (one step for DD, two for TD / QD).
-template <int K>
+template <int K, int AR = AR_BF>
 __device__ __forceinline__ mpn<double, K> mp_recip(const mpn<double, K>& d) {
     const auto one = mp_from<double, K>(1.0);
     auto y = mp_from<double, K>(1.0 / d.c[0]);
     constexpr int steps = K == 2 ? 1 : 2;
 #pragma unroll
     for (int s = 0; s < steps; ++s) {
-        const auto e = bf_sub(one, bf_mul(d, y));
-        y = bf_add(y, bf_mul(y, e));
+        const auto e = ar_sub<AR>(one, ar_mul<AR>(d, y));
+        y = ar_add<AR>(y, ar_mul<AR>(y, e));
     }
     return y;
 }
 
 // x / y = (x conj y) (1 / |y|^2).
-template <int K>
+template <int K, int AR = AR_BF>
 __device__ __forceinline__ cplx<K> c_div(const cplx<K>& x, const cplx<K>& y) {
-    const auto den = bf_add(bf_mul(y.re, y.re), bf_mul(y.im, y.im));
-    const auto inv = mp_recip<K>(den);
-    const auto nr = bf_add(bf_mul(x.re, y.re), bf_mul(x.im, y.im));
-    const auto ni = bf_sub(bf_mul(x.im, y.re), bf_mul(x.re, y.im));
-    return {bf_mul(nr, inv), bf_mul(ni, inv)};
+    const auto den = ar_add<AR>(ar_mul<AR>(y.re, y.re), ar_mul<AR>(y.im, y.im));
+    const auto inv = mp_recip<K, AR>(den);
+    const auto nr = ar_add<AR>(ar_mul<AR>(x.re, y.re), ar_mul<AR>(x.im, y.im));
+    const auto ni = ar_sub<AR>(ar_mul<AR>(x.im, y.re), ar_mul<AR>(x.re, y.im));
+    return {ar_mul<AR>(nr, inv), ar_mul<AR>(ni, inv)};
 }
 
 // Component-wise select (a select on whole aggregates would go through memory).
@@ -311,7 +312,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 
 // Prologue, one wave per polynomial: monic coefficients c_i = a_i / a_n and,
 // with init, the Aberth start values (binary64, leading components).
-template <int K>
+template <int K, int AR>
 __global__ void __launch_bounds__(64)
 k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
               const double* __restrict__ aim, long long psc, double* rre, double* rim,
@@ -323,7 +324,7 @@ k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
         const long long co = P.coef_off[b], ro = P.root_off[b];
         const C an = c_load<K>(are, aim, psc, co + n);
         for (int i = lane; i < n; i += 64)
-            c_store<K>(P.mre, P.mim, P.psm, co + i, c_div<K>(c_load<K>(are, aim, psc, co + i), an));
+            c_store<K>(P.mre, P.mim, P.psm, co + i, c_div<K, AR>(c_load<K>(are, aim, psc, co + i), an));
         if (!init) continue;
         __syncthreads();
         int nnz = 0;
@@ -353,7 +354,7 @@ k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
 }
 
 // Persistent iteration kernel: waves pull polynomials in LPT order.
-template <int K, int R>
+template <int K, int R, int AR>
 __global__ void __launch_bounds__(64)
 k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr, int* status,
                 int iters) {
@@ -397,7 +398,7 @@ k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr,
                     const C ck = c_load<K>(mre, mim, P.psm, k);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        h[r] = c_add<K>(c_mul<K>(h[r], z[r]), c_ldexp<K>(ck, clamp_exp(-E[r])));
+                        h[r] = c_add<K, AR>(c_mul<K, AR>(h[r], z[r]), c_ldexp<K>(ck, clamp_exp(-E[r])));
                         c_rescale<K, true>(h[r], E[r]);
                     }
                 }
@@ -415,7 +416,7 @@ k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr,
                     const C zj = c_load<K>(sre, sim, pss, ro + j);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        C t = c_mul<K>(Pp[r], c_sub<K>(z[r], zj));
+                        C t = c_mul<K, AR>(Pp[r], c_sub<K, AR>(z[r], zj));
                         long long Ft = F[r];
                         c_rescale<K, false>(t, Ft);
                         const bool take = j != idx[r];
@@ -425,8 +426,8 @@ k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr,
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const C w = c_ldexp<K>(c_div<K>(h[r], Pp[r]), clamp_exp(E[r] - F[r]));
-                    if (idx[r] < n) c_store<K>(dre, dim, psd, ro + idx[r], c_sub<K>(z[r], w));
+                    const C w = c_ldexp<K>(c_div<K, AR>(h[r], Pp[r]), clamp_exp(E[r] - F[r]));
+                    if (idx[r] < n) c_store<K>(dre, dim, psd, ro + idx[r], c_sub<K, AR>(z[r], w));
                 }
             }
             __syncthreads();  // iterate t complete before t+1 reads it
@@ -482,7 +483,7 @@ struct mpx_plan_s {
 
 namespace mpx {
 
-template <int K, int R>
+template <int K, int R, int AR>
 static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long long psc, void* rre,
                        void* rim, long long psr, int* status, int waves_cu, hipStream_t s) {
     k_reset_counter<<<1, 1, 0, s>>>(p->d.counter);
@@ -491,12 +492,12 @@ static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long lon
     long long grid = (long long)p->cus * waves_cu;
     if (grid > p->batch) grid = p->batch;
     if (grid < 1) grid = 1;
-    k_dk_prologue<K><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (const double*)are,
+    k_dk_prologue<K, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (const double*)are,
                                                   (const double*)aim, psc, (double*)rre,
                                                   (double*)rim, psr,
                                                   (p->flags & MPX_DK_INIT) ? 1 : 0);
     if ((st = launch_status())) return st;
-    k_durand_kerner<K, R><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
+    k_durand_kerner<K, R, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
                                                         (double*)rim, psr, status, p->iters);
     return launch_status();
 }
@@ -504,15 +505,21 @@ static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long lon
 static int launch_dk(mpx_plan_s* p, int variant, const void* are, const void* aim, long long psc,
                      void* rre, void* rim, long long psr, int* status, hipStream_t s) {
     const DkVariant v = kDkVariants[variant];
-#define MPX_DK_CASE(KK)                                                                        \
-    if (p->K == KK) {                                                                          \
-        if (v.r == 1) return launch_dk_t<KK, 1>(p, are, aim, psc, rre, rim, psr, status,      \
-                                                v.waves_cu, s);                                \
-        return launch_dk_t<KK, 2>(p, are, aim, psc, rre, rim, psr, status, v.waves_cu, s);    \
+#define MPX_DK_CASE(KK, AR_)                                                                   \
+    if (p->K == KK && ar == AR_) {                                                             \
+        if (v.r == 1) return launch_dk_t<KK, 1, AR_>(p, are, aim, psc, rre, rim, psr, status, \
+                                                     v.waves_cu, s);                           \
+        return launch_dk_t<KK, 2, AR_>(p, are, aim, psc, rre, rim, psr, status, v.waves_cu,   \
+                                       s);                                                     \
     }
-    MPX_DK_CASE(2)
-    MPX_DK_CASE(3)
-    MPX_DK_CASE(4)
+    const int ar = arith_of(p->prec);
+    MPX_DK_CASE(2, AR_BF)
+    MPX_DK_CASE(3, AR_BF)
+    MPX_DK_CASE(4, AR_BF)
+    MPX_DK_CASE(2, AR_NOBF)
+    MPX_DK_CASE(3, AR_NOBF)
+    MPX_DK_CASE(4, AR_NOBF)
+    MPX_DK_CASE(2, AR_NOBF_ACC)
 #undef MPX_DK_CASE
     return MPX_EPREC;
 }
@@ -628,7 +635,7 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
                                   const int32_t* degree_host, int iters, uint32_t flags) {
     if (out == nullptr) return MPX_EINVAL;
     *out = nullptr;
-    if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
+    if (!prec_k_ar(prec) || base_prec(prec) == MPX_FF) return MPX_EPREC;
     if (batch < 0 || batch > INT32_MAX || (degree_host == nullptr && batch > 0) || iters < 0)
         return MPX_EINVAL;
     if (flags & ~(uint32_t)(MPX_DK_INIT | MPX_DK_GRAPH)) return MPX_EINVAL;
@@ -648,7 +655,7 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     auto* p = new (std::nothrow) mpx_plan_s();
     if (!p) return MPX_EINVAL;
     p->prec = prec;
-    p->K = prec_k(prec);
+    p->K = prec_k_ar(prec);
     p->batch = (int)batch;
     p->iters = iters;
     p->flags = flags;

@@ -1,7 +1,7 @@
 """GPU parity of the conventional ("NoBF") arithmetic against the CPU oracle
 run with the same arithmetic: elementwise add / mul, AXPY, GEMM (every tile
-variant, every transpose) and real Horner must match bit for bit; dot stays
-within the usual bound.  Mixed inputs put integer-valued numbers (whose
+variant, every transpose), real Horner and Durand-Kerner sweeps must match
+bit for bit; dot stays within the usual bound.  Mixed inputs put integer-valued numbers (whose
 renormalisation takes the zero-error paths) and random ones in the same
 wavefronts, so lanes of one wave take different paths."""
 from fractions import Fraction
@@ -140,3 +140,49 @@ def test_flags_rejected_where_not_supported():
     assert L.mpx_add(mpx.QD | mpx.NOBF_ACC, 1, x.data_ptr(), 4, x.data_ptr(), 4, x.data_ptr(), 4,
                      None) == -2
     assert L.mpx_gemm_variant_count(mpx.DD | mpx.NOBF | mpx.NOBF_ACC) == 0
+
+
+def _dk_inputs(K, degrees, seed):
+    degrees = np.asarray(degrees, np.int32)
+    total = int((degrees + 1).sum())
+    return degrees, synth.mp_array(K, total, seed, "N"), synth.mp_array(K, total, seed + 1, "N")
+
+
+@pytest.mark.parametrize("p,K,mode", MODES)
+def test_dk_iterations_bit_exact(p, K, mode):
+    """Durand-Kerner with the conventional arithmetic: the monic prologue and
+    six Jacobi sweeps from the oracle's start values match bit for bit, for
+    every launch variant."""
+    deg, cre, cim = _dk_inputs(K, [1, 2, 3, 17, 64, 65, 130, 5, 40], 110 + K)
+    with oracle.arith(mode):
+        z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+        wr, wi, wst = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=6, init=False)
+    for v in range(mpx.polyroots_variant_count()):
+        plan = mpx.RootsPlan(p, deg, iters=6, init=False, graph=False)
+        plan.set_variant(v)
+        zr, zi = to_gpu(z0r), to_gpu(z0i)
+        st = plan.run(to_gpu(cre), to_gpu(cim), zr, zi)
+        assert bits_equal(to_np(zr), wr), (v, first_mismatch(to_np(zr), wr))
+        assert bits_equal(to_np(zi), wi), v
+        assert np.array_equal(to_np(st), wst)
+
+
+@pytest.mark.parametrize("p,K", [("qd_nobf", 4), ("td_nobf", 3)])
+def test_dk_chebyshev_roots_nobf(p, K):
+    """Chebyshev integration polynomial n = 8 (Section 4.2) solved with the
+    conventional arithmetic: the same nodes as the BF solver finds, symmetric
+    about 0, all sweeps finite."""
+    n = 8
+    a = synth.chebyshev_coefficients(n)
+    cre = np.stack([synth.round_greedy(c, K) for c in a], axis=1)
+    cim = np.zeros_like(cre)
+    deg = np.array([n], np.int32)
+    out = {}
+    for q in (p, p.split("_")[0]):
+        zr = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+        zi = torch.zeros_like(zr)
+        st = mpx.RootsPlan(q, deg, iters=200, init=True, graph=False).run(to_gpu(cre), to_gpu(cim), zr, zi)
+        assert int(to_np(st)[0]) == 0
+        out[q] = np.sort(to_np(zr)[0])
+    assert np.max(np.abs(out[p] - out[p.split("_")[0]])) < 1e-15
+    assert np.max(np.abs(out[p] + out[p][::-1])) < 1e-15

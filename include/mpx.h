@@ -64,7 +64,8 @@ typedef enum {
  *                 TW / QW renormalisation with data-dependent tests;
  *   MPX_NOBF_ACC  DD only: DWAccurateAdd in place of DWAdd.
  * Accepted by mpx_add, mpx_mul, mpx_axpy, mpx_dot, mpx_gemm (and its variant,
- * variant-count/name and autotune calls) and mpx_polyval; every other entry
+ * variant-count/name and autotune calls), mpx_polyval and mpx_polyroots_plan
+ * (the plan then runs Durand-Kerner in that arithmetic); every other entry
  * point, and any flag on MPX_FF, returns MPX_EPREC.  Results of the
  * conventional operations are deterministic and meet the same error bounds
  * as the branch-free ones except that the sloppy DD addition is accurate

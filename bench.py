@@ -213,6 +213,22 @@ def vector_rows(mpx, torch, T):
                 "dot_us": t_dot * 1e3, "dot_GB_s": b_dot / (t_dot * 1e-3) / 1e9,
                 "dot_frac_hbm": b_dot / (t_dot * 1e-3) / PEAK_HBM,
             }
+            if n == 4096:
+                # launch-bound size: the same calls captured 100 at a time in
+                # one HIP graph and replayed (per-call time and calls/s)
+                calls = 100
+                for name, fn in (("axpy", lambda: mpx.axpy(p, alpha, x, y)),
+                                 ("dot", lambda: mpx.dot(p, x, y, out=r, ws=ws))):
+                    g = torch.cuda.CUDAGraph()
+                    fn()
+                    torch.cuda.synchronize()
+                    with torch.cuda.graph(g):
+                        for _ in range(calls):
+                            fn()
+                    tg = T(lambda: g.replay(), reps=10) / calls
+                    row[str(n)][f"{name}_graph_us"] = tg * 1e3
+                    row[str(n)][f"{name}_graph_calls_per_s"] = 1.0 / (tg * 1e-3)
+                    del g
         out[p] = row
     return out
 

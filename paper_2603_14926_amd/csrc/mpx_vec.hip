@@ -135,9 +135,13 @@ k_sum_parts(long long nparts, const T* __restrict__ part, long long psp, T* __re
 }
 
 // Number of stage-1 blocks: a function of n alone (the summation tree, and so
-// the rounding, depends on it).  Small vectors use one block and no stage 2.
+// the rounding, depends on it).  Up to one block's worth of elements uses one
+// block and no stage 2; up to 64 Ki elements, one element per thread (the
+// dependent multiply-add chain per thread is what bounds small dots); beyond,
+// four or more per thread.
 static long long dot_blocks(long long n) {
-    if (n <= 16 * kBlock) return 1;
+    if (n <= kBlock) return 1;
+    if (n <= 256LL * kBlock) return ceil_div(n, kBlock);
     long long b = ceil_div(n, 4LL * kBlock);
     return b > 2048 ? 2048 : b;
 }

@@ -72,7 +72,7 @@ def _within_bound(p, got, x, y):
 
 
 @pytest.mark.parametrize("p,K,dt", PREC_K)
-@pytest.mark.parametrize("n", [0, 1, 2, 4096, 4097, 100003, 1 << 20])
+@pytest.mark.parametrize("n", [0, 1, 2, 256, 257, 4096, 4097, 65536, 65537, 100003, 1 << 20])
 def test_dot_within_bound(p, K, dt, n):
     x = _vec(K, n, 10 + n % 97, dt, "W")
     y = _vec(K, n, 20 + n % 89, dt, "W")
@@ -223,3 +223,36 @@ def test_gemm_autotune_keeps_bits():
     v, ms = mpx.gemm_autotune("qd", A, B, out, reps=1)
     assert 0 <= v < len(mpx.gemm_variants("qd")) and ms > 0
     assert bits_equal(to_np(mpx.gemm("qd", A, B)), ref)
+
+
+def test_graph_captured_axpy_and_dot_replay():
+    """Launch-bound n = 4096 calls captured in one HIP graph: every replay
+    (with eager work and synchronisation between replays) matches the oracle
+    applied the same number of times."""
+    K, n, per = 4, 4096, 3
+    x = _vec(K, n, 501, np.float64)
+    y0 = _vec(K, n, 502, np.float64)
+    alpha = [0.75, 2.0 ** -60, 0.0, 0.0]
+    gx, gy = to_gpu(x), to_gpu(y0)
+    r = torch.empty(K, dtype=torch.float64, device="cuda")
+    ws = mpx.workspace(mpx.OP_DOT, "qd", n)
+    mpx.axpy("qd", alpha, gx, gy)      # warm-up outside the capture
+    torch.cuda.synchronize()
+    gy.copy_(to_gpu(y0))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per):
+            mpx.axpy("qd", alpha, gx, gy)
+        mpx.dot("qd", gx, gy, out=r, ws=ws)
+    torch.cuda.synchronize()
+    gy.copy_(to_gpu(y0))
+    want_y = y0.copy()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 3).sum().item()   # eager work between replays
+        for _ in range(per):
+            want_y = oracle.axpy(K, np.array(alpha), x, want_y)
+        assert bits_equal(to_np(gy), want_y), rep
+        ok, err, bound = _within_bound("qd", to_np(r), x, want_y)
+        assert ok, (rep, err, bound)

@@ -64,8 +64,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
-                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "durand_kerner", "autograd",
-                             "ozaki"],
+                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "strassen", "durand_kerner",
+                             "autograd", "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -319,6 +319,43 @@ def nobf_rows(mpx, torch, T):
     return out
 
 
+# -------------------------------------------------------------- Strassen ----
+
+def strassen_rows(mpx, torch, T):
+    """Strassen's recursion (the scheme Section 3.1 benchmarks) against the
+    classical product at the same size; cutoff 2048: one level at n = 2048,
+    two at 4096, leaves of 1024^3 on the tuned GEMM.  Also BF against
+    conventional arithmetic under Strassen at n = 2048 (Table 4's pairing)."""
+    from paper_2603_14926_amd import synth
+    out = {}
+    runs = [("qd", 2048), ("qd", 4096), ("td", 2048), ("td", 4096), ("dd", 2048), ("dd", 4096),
+            ("qd_nobf", 2048), ("td_nobf", 2048)]
+    times = {}
+    for p, n in runs:
+        cutoff, leaf = 2048, 1024
+        K = mpx.ncomp(p)
+        A = gpu_mp(torch, K, (n, n), synth.seed_for(1, 0))
+        B = gpu_mp(torch, K, (n, n), synth.seed_for(1, 1))
+        Cm = torch.empty_like(A)
+        ws = mpx.workspace(mpx.OP_STRASSEN, p, n, n, n, cutoff)
+        mpx.gemm_autotune(p, A[:, :leaf, :leaf], B[:, :leaf, :leaf], Cm[:, :leaf, :leaf], reps=1)
+        ts = T(lambda: mpx.gemm_strassen(p, A, B, cutoff, out=Cm, ws=ws), reps=2)
+        mpx.gemm_autotune(p, A, B, Cm, reps=1)
+        tc = T(lambda: mpx.gemm(p, A, B, out=Cm), reps=2)
+        times[(p, n)] = ts
+        levels = 0
+        d = n
+        while d >= cutoff:
+            d = (d + 1) // 2
+            levels += 1
+        out[f"{p}_{n}"] = {"strassen_ms": ts, "classic_ms": tc, "speedup": tc / ts, "levels": levels,
+                           "cutoff": cutoff, "classical_mp_op_s": 2.0 * n ** 3 / (ts * 1e-3)}
+        del A, B, Cm, ws
+    for q in ("qd", "td"):
+        out[f"{q}_2048"]["speedup_bf_over_nobf"] = times[(q + "_nobf", 2048)] / times[(q, 2048)]
+    return out
+
+
 # ------------------------------------------------------------ complex 3M ----
 
 def cgemm_rows(mpx, torch, T):
@@ -541,6 +578,7 @@ def main():
               "cgemm": lambda: cgemm_rows(mpx, torch, T),
               "polyeval": lambda: polyeval_rows(mpx, torch, T),
               "nobf": lambda: nobf_rows(mpx, torch, T),
+              "strassen": lambda: strassen_rows(mpx, torch, T),
               "durand_kerner": lambda: dk_row(mpx, torch, T),
               "autograd": lambda: autograd_row(mpx, torch, T),
               "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
@@ -613,6 +651,7 @@ def main():
         log("complex 3M"); rows["cgemm_3m"] = cgemm_rows(mpx, torch, T)
         log("horner vs estrin"); rows["polyeval"] = polyeval_rows(mpx, torch, T)
         log("bf vs nobf"); rows["bf_vs_nobf"] = nobf_rows(mpx, torch, T)
+        log("strassen"); rows["strassen"] = strassen_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
         rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))

@@ -64,7 +64,8 @@ typedef enum {
  *                 TW / QW renormalisation with data-dependent tests;
  *   MPX_NOBF_ACC  DD only: DWAccurateAdd in place of DWAdd.
  * Accepted by mpx_add, mpx_mul, mpx_axpy, mpx_dot, mpx_gemm (and its variant,
- * variant-count/name and autotune calls), mpx_polyval and mpx_polyroots_plan
+ * variant-count/name and autotune calls), mpx_gemm_strassen, mpx_polyval and
+ * mpx_polyroots_plan
  * (the plan then runs Durand-Kerner in that arithmetic); every other entry
  * point, and any flag on MPX_FF, returns MPX_EPREC.  Results of the
  * conventional operations are deterministic and meet the same error bounds
@@ -101,11 +102,13 @@ int mpx_axpy(int prec, int64_t n, const void *alpha_host, const void *x, int64_t
 
 /* --------------------------------------------------------------- reductions --
  * Workspace sizes (bytes) for the calls that need one; op codes: */
-enum { MPX_OP_DOT = 1, MPX_OP_GEMV = 2, MPX_OP_GEMM = 3, MPX_OP_OZAKI = 4, MPX_OP_CGEMM = 5 };
+enum { MPX_OP_DOT = 1, MPX_OP_GEMV = 2, MPX_OP_GEMM = 3, MPX_OP_OZAKI = 4, MPX_OP_CGEMM = 5,
+       MPX_OP_STRASSEN = 6 };
 /* For MPX_OP_DOT: m = n (vector length).  MPX_OP_GEMV: m, n = matrix shape,
  * k = trans.  MPX_OP_GEMM: 0.  MPX_OP_OZAKI: m, n, k = GEMM shape,
- * extra = number of slices.  MPX_OP_CGEMM: m, n, k = GEMM shape.  Returns 0
- * for invalid arguments. */
+ * extra = number of slices.  MPX_OP_CGEMM: m, n, k = GEMM shape.
+ * MPX_OP_STRASSEN: m, n, k = GEMM shape, extra = cutoff (arithmetic flags
+ * allowed).  Returns 0 for invalid arguments. */
 size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k, int64_t extra);
 
 /* result[0..K-1] (device, K contiguous values) = sum_i x_i * y_i.
@@ -147,6 +150,25 @@ int mpx_cgemm_3m(int prec, int64_t m, int64_t n, int64_t k, const void *Are, con
                  int64_t lda, int64_t psA, const void *Bre, const void *Bim, int64_t ldb,
                  int64_t psB, void *Cre, void *Cim, int64_t ldc, int64_t psC, void *ws,
                  size_t ws_bytes, void *stream);
+
+/* C := A B (A m x k, B k x n, row-major planes, no transposes) by Strassen's
+ * recursion, the scheme Section 3.1 benchmarks (there with cutoff 32):
+ *   M1 = (A11+A22)(B11+B22)  M2 = (A21+A22) B11  M3 = A11 (B12-B22)
+ *   M4 = A22 (B21-B11)       M5 = (A11+A12) B22  M6 = (A21-A11)(B11+B12)
+ *   M7 = (A12-A22)(B21+B22)
+ *   C11 = ((M1+M4)-M5)+M7   C12 = M3+M5   C21 = M2+M4   C22 = ((M1-M2)+M3)+M6
+ * A product splits while min(m, k, n) >= cutoff (cutoff >= 2); a dimension d
+ * splits into ceil(d/2) + floor(d/2), trailing blocks zero-padded to the
+ * leading block's shape; leaves are mpx_gemm (sequential k per entry); sums
+ * are the multicomponent addition (a difference adds the negation).  DD, TD,
+ * QD, with or without the arithmetic flags (not FF).  ws: at least
+ * mpx_workspace_size(MPX_OP_STRASSEN, prec, m, n, k, cutoff) bytes (0 when
+ * no split happens).  C must not overlap A, B or ws.  More than 8 levels of
+ * recursion return MPX_ENOTSUP.  The error bound is norm-wise (Strassen's
+ * method is not componentwise accurate). */
+int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                      int64_t psA, const void *B, int64_t ldb, int64_t psB, void *C, int64_t ldc,
+                      int64_t psC, int64_t cutoff, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------- GEMM tuning --
  * The GEMM has several register/LDS tilings ("variants"); all produce the

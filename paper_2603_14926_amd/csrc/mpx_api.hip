@@ -19,7 +19,8 @@ extern "C" const char* mpx_status_string(int status) {
 extern "C" size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k,
                                      int64_t extra) {
     using namespace mpx;
-    if (op == MPX_OP_DOT ? !prec_k_ar(prec) : (op != MPX_OP_OZAKI && !prec_k(prec))) return 0;
+    const bool flags_ok = op == MPX_OP_DOT || op == MPX_OP_STRASSEN;
+    if (flags_ok ? !prec_k_ar(prec) : (op != MPX_OP_OZAKI && !prec_k(prec))) return 0;
     if (m < 0 || n < 0 || k < 0 || extra < 0) return 0;
     switch (op) {
         case MPX_OP_DOT: return dot_workspace(prec, m);
@@ -27,6 +28,7 @@ extern "C" size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int
         case MPX_OP_GEMM: return 0;
         case MPX_OP_OZAKI: return ozaki_workspace(m, n, k, (int)extra);
         case MPX_OP_CGEMM: return cgemm_workspace(prec, m, n, k);
+        case MPX_OP_STRASSEN: return strassen_workspace(prec, m, n, k, extra);
         default: return 0;
     }
 }

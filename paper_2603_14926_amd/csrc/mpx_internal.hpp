@@ -58,4 +58,5 @@ size_t dot_workspace(int prec, long long n);
 size_t gemv_workspace(int prec, long long m, long long n, int trans);
 size_t ozaki_workspace(long long m, long long n, long long k, int slices);
 size_t cgemm_workspace(int prec, long long m, long long n, long long k);
+size_t strassen_workspace(int prec, long long m, long long n, long long k, long long cutoff);
 }  // namespace mpx

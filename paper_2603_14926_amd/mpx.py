@@ -27,7 +27,7 @@ PRECS = {"dd": DD, "td": TD, "qd": QD, "ff": FF,
          "dd_nobf_acc": DD | NOBF_ACC}
 _K = {DD: 2, TD: 3, QD: 4, FF: 2, DD | NOBF: 2, TD | NOBF: 3, QD | NOBF: 4, DD | NOBF_ACC: 2}
 
-OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI, OP_CGEMM = 1, 2, 3, 4, 5
+OP_DOT, OP_GEMV, OP_GEMM, OP_OZAKI, OP_CGEMM, OP_STRASSEN = 1, 2, 3, 4, 5, 6
 
 _lib = None
 
@@ -76,6 +76,7 @@ def _declare(L):
     sig("mpx_gemm_autotune_reset", None)
     sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
+    sig("mpx_gemm_strassen", _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _l, _v, _z, _v)
     sig("mpx_cgemm_3m", _i, _i, _l, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _z, _v)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_estrin", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
@@ -292,6 +293,23 @@ def cgemm_3m(p, Are, Aim, Bre, Bim, out=None, ws=None):
                               _ptr(Bim), max(ldb, n), psB, _ptr(Cre), _ptr(Cim), max(ldc, n), psC,
                               _ptr(ws), ws.numel(), _stream()), "mpx_cgemm_3m")
     return Cre, Cim
+
+
+def gemm_strassen(p, A, B, cutoff, out=None, ws=None):
+    """C = A B by Strassen's recursion (split while min(m, k, n) >= cutoff)."""
+    p = prec_of(p)
+    psA, lda = _planes(A, p, 2, "A")
+    psB, ldb = _planes(B, p, 2, "B")
+    m, n, k = _gemm_shapes(A, B, False, False)
+    if out is None:
+        out = torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=A.device)
+    psC, ldc = _planes(out, p, 2, "out")
+    if ws is None:
+        ws = workspace(OP_STRASSEN, p, m, n, k, cutoff)
+    _check(lib().mpx_gemm_strassen(p, m, n, k, _ptr(A), max(lda, k), psA, _ptr(B), max(ldb, n), psB,
+                                   _ptr(out), max(ldc, n), psC, int(cutoff), _ptr(ws), ws.numel(),
+                                   _stream()), "mpx_gemm_strassen")
+    return out
 
 
 def gemm_ozaki_set_variant(v: int) -> None:

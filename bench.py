@@ -508,7 +508,10 @@ def rel_errors(A, B, Cm, rows, cols):
 # Ozaki candidates in order of cost (slice-pair products s(s+1)/2): beta = 22
 # (22 bits per slice, exact level sums with kblk = 256 up to 6 slices), then
 # beta = 20 for more slices.
-OZAKI_CANDIDATES = [(4, 22), (5, 22), (6, 22), (7, 20), (8, 20), (9, 20), (10, 20), (11, 20), (12, 20)]
+# (slices, beta, kblk), each meeting kblk 2^(2 beta) (1 + max(0, s-2)/4) <= 2^53
+# so the slice products are exact; ordered by cost (slice pairs, then folds).
+OZAKI_CANDIDATES = [(4, 22, 256), (5, 22, 256), (6, 22, 256), (6, 23, 64), (7, 22, 128),
+                    (8, 22, 128), (9, 22, 128), (10, 22, 128), (12, 22, 128)]
 
 
 def ozaki_row(mpx, torch, T, sizes):
@@ -530,28 +533,28 @@ def ozaki_row(mpx, torch, T, sizes):
             bound = n * 2.0 ** -104
             chosen, sweep = None, {}
             Coz = torch.empty_like(A)
-            for (s, beta) in OZAKI_CANDIDATES:
+            for (s, beta, kblk) in OZAKI_CANDIDATES:
                 ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
-                mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=256, out=Coz, ws=ws)
+                mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=kblk, out=Coz, ws=ws)
                 err = rel_errors(A_np, B_np, Coz.cpu().numpy(), rows, cols)
-                sweep[(s, beta)] = err
+                sweep[(s, beta, kblk)] = err
                 del ws
                 if err <= bound and chosen is None:
-                    chosen = (s, beta)
+                    chosen = (s, beta, kblk)
                 if err <= err_bf:
                     break
-            s_eq = next(((s, b) for (s, b), e in sweep.items() if e <= err_bf), None)
+            s_eq = next((c for c, e in sweep.items() if e <= err_bf), None)
             res = {"bf_dd_ms": t_bf, "bf_dd_max_rel_err": err_bf, "bound": bound,
-                   "error_by_slices": {f"s{s}_beta{b}": v for (s, b), v in sweep.items()},
-                   "sampled_entries": int(rows.size), "kblk": 256}
+                   "error_by_slices": {f"s{s}_beta{b}_kblk{kb}": v for (s, b, kb), v in sweep.items()},
+                   "sampled_entries": int(rows.size)}
             for tag, cfg in (("at_bound", chosen), ("at_bf_error", s_eq)):
                 if cfg is None:
                     continue
-                s, beta = cfg
+                s, beta, kblk = cfg
                 ws = mpx.workspace(mpx.OP_OZAKI, "dd", n, n, n, s)
-                t = T(lambda: mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=256, out=Coz, ws=ws), reps=2)
+                t = T(lambda: mpx.gemm_ozaki_dd(A, B, s, beta=beta, kblk=kblk, out=Coz, ws=ws), reps=2)
                 prods = s * (s + 1) / 2
-                res[tag] = {"slices": s, "beta": beta, "ms": t, "max_rel_err": sweep[cfg],
+                res[tag] = {"slices": s, "beta": beta, "kblk": kblk, "ms": t, "max_rel_err": sweep[cfg],
                             "frac_mfma_peak": prods * 2.0 * n ** 3 / (t * 1e-3) / PEAK_MFMA_F64,
                             "speedup_vs_bf_dd": t_bf / t}
                 del ws

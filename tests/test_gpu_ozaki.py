@@ -55,3 +55,15 @@ def test_ozaki_4096_sampled_error_and_parity(phi):
         sc = exact.abs_dot(A[:, rows[t], :], B[:, :, cols[t]])
         err = float(abs(exact.value(got[:, rows[t], cols[t]]) - ex)) / sc
         assert err <= n * 2.0 ** -104, (phi, t, err)
+
+
+@pytest.mark.parametrize("s,beta,kblk", [(6, 23, 64), (7, 22, 128), (9, 22, 128)])
+def test_ozaki_wider_slices_smaller_blocks_bit_exact(s, beta, kblk):
+    """The benchmark's other exact (slices, beta, k-block) choices."""
+    m, n, k = 70, 45, 300
+    A = synth.mp_array(2, (m, k), 600 + s, "W", phi=8.0)
+    B = synth.mp_array(2, (k, n), 700 + s, "W", phi=8.0)
+    got = to_np(mpx.gemm_ozaki_dd(to_gpu(A), to_gpu(B), s, beta=beta, kblk=kblk))
+    rows, cols = np.divmod(np.arange(m * n), n)
+    want = oracle.ozaki_entries(A, B, rows, cols, s=s, beta=beta, kblk=kblk).reshape(2, m, n)
+    assert bits_equal(got, want), first_mismatch(got, want)

@@ -13,7 +13,7 @@ from oracle import exact
 from paper_2603_14926_amd import synth
 
 
-@pytest.mark.parametrize("phi,beta", [(1.0, 20), (8.0, 20), (1.0, 22), (8.0, 22)])
+@pytest.mark.parametrize("phi,beta", [(1.0, 20), (8.0, 20), (1.0, 22), (8.0, 22), (1.0, 23), (8.0, 23)])
 def test_split_is_error_free_and_bounded(phi, beta):
     s = 9
     A = synth.mp_array(2, (6, 40), 1, "W", phi=phi)

@@ -169,14 +169,14 @@ static int launch_dot(long long n, const void* x, long long psx, const void* y, 
 // chunk; lane l walks columns c0 + l, c0 + l + 64, ... sequentially with R
 // accumulators, reusing each x_j for its R rows; the wave butterfly then sums
 // the 64 lane partials of each row.
-constexpr int kGemvRows = 2;
+constexpr int kGemvRows = 4;
 
 template <typename T, int K, int R>
 __global__ void __launch_bounds__(kBlock)
 k_gemv_n(long long m, long long n, const T* __restrict__ A, long long lda, long long psA,
          const T* __restrict__ x, long long psx, T* __restrict__ out, long long pso,
          long long chunk) {
-    constexpr int U = 4;  // columns per lane whose loads are issued together
+    constexpr int U = 2;  // columns per lane whose loads are issued together
     const int lane = threadIdx.x & 63;
     const long long wave = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const long long r0 = wave * R;

@@ -332,6 +332,18 @@ def polyval_estrin(K, coef, x):
     return y
 
 
+def polyval_cplx(K, coef, xre, xim, method="horner"):
+    """Real-coefficient polynomials (coef (K, batch, deg+1)) at complex
+    points (xre, xim each (K, batch)) by Horner or Estrin; returns (yre, yim)."""
+    coef = _chk(coef, K); xre = _chk(xre, K); xim = _chk(xim, K)
+    batch, d1 = coef.shape[1], coef.shape[2]
+    yre = np.zeros((K, batch)); yim = np.zeros((K, batch))
+    fn = lib().orc_polyval_cplx if method == "horner" else lib().orc_polyval_cplx_estrin
+    fn(_i32(K), _i64(batch), _i64(d1 - 1), _p(coef), _i64(batch * d1), _p(xre), _p(xim),
+       _i64(batch), _p(yre), _p(yim), _i64(batch))
+    return yre, yim
+
+
 def polyval_backward(K, coef, x, g, want_coef=True, want_x=True):
     """Gradients of sum_b g_b p_b(x_b): (dcoef (K,batch,deg+1), dx (K,batch))."""
     coef = _chk(coef, K); x = _chk(x, K); g = _chk(g, K)

@@ -922,6 +922,80 @@ void orc_cdiv(int K, const double *xr, const double *xi, const double *yr,
     memcpy(zr, z.re, 8 * K); memcpy(zi, z.im, 8 * K);
 }
 
+/* Real-coefficient polynomial at complex arguments (Section 4.1, the second
+ * polynomial benchmark).  Horner: h = (a_n, 0); h := h * z + a_i for
+ * i = n-1 .. 0, the complex product in the 4M form above and the real
+ * coefficient added to the real part only (the imaginary part is left as
+ * is).  Coefficient planes as in orc_polyval; z and the result as separate
+ * real / imaginary planes. */
+void orc_polyval_cplx(int K, int64_t batch, int64_t deg, const double *coef, int64_t psc,
+                      const double *xre, const double *xim, int64_t psx, double *yre,
+                      double *yim, int64_t psy) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < batch; b++) {
+        const int64_t off = b * (deg + 1);
+        cmp z, h;
+        double a[4];
+        gather(K, xre, psx, b, z.re);
+        gather(K, xim, psx, b, z.im);
+        memset(&h, 0, sizeof(h));
+        gather(K, coef, psc, off + deg, h.re);
+        for (int64_t i = deg - 1; i >= 0; i--) {
+            cmp_mul(K, &h, &z, &h);
+            gather(K, coef, psc, off + i, a);
+            mp_add(K, h.re, a, h.re);
+        }
+        scatter(K, yre, psy, b, h.re);
+        scatter(K, yim, psy, b, h.im);
+    }
+}
+
+/* Estrin's method at complex arguments: the coefficient list padded with
+ * zeros to N = 2^L; the first level pairs real coefficients,
+ * c'_j = (a_2j + a_{2j+1} x_re, a_{2j+1} x_im) (a real times a complex
+ * number is two products); later levels are complex,
+ * c'_j = c_2j + c_{2j+1} X with the 4M product and componentwise sums;
+ * X := X^2 (4M) after every level. */
+void orc_polyval_cplx_estrin(int K, int64_t batch, int64_t deg, const double *coef,
+                             int64_t psc, const double *xre, const double *xim, int64_t psx,
+                             double *yre, double *yim, int64_t psy) {
+    int64_t N = 1;
+    while (N < deg + 1) N *= 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < batch; b++) {
+        const int64_t off = b * (deg + 1);
+        double *a = (double *)calloc((size_t)N * 4, sizeof(double));
+        cmp *c = (cmp *)calloc((size_t)(N > 1 ? N / 2 : 1), sizeof(cmp));
+        cmp X, t;
+        for (int64_t i = 0; i <= deg; i++) gather(K, coef, psc, off + i, &a[4 * i]);
+        gather(K, xre, psx, b, X.re);
+        gather(K, xim, psx, b, X.im);
+        if (N == 1) {
+            memset(&c[0], 0, sizeof(cmp));
+            memcpy(c[0].re, a, sizeof(double) * K);
+        } else {
+            for (int64_t j = 0; j < N / 2; j++) {
+                double p[4];
+                mp_mul(K, &a[4 * (2 * j + 1)], X.re, p);
+                mp_add(K, &a[4 * (2 * j)], p, c[j].re);
+                mp_mul(K, &a[4 * (2 * j + 1)], X.im, c[j].im);
+            }
+            cmp_mul(K, &X, &X, &X);
+            for (int64_t len = N / 2; len > 1; len /= 2) {
+                for (int64_t j = 0; j < len / 2; j++) {
+                    cmp_mul(K, &c[2 * j + 1], &X, &t);
+                    cmp_add(K, &c[2 * j], &t, &c[j]);
+                }
+                cmp_mul(K, &X, &X, &X);
+            }
+        }
+        scatter(K, yre, psy, b, c[0].re);
+        scatter(K, yim, psy, b, c[0].im);
+        free(a);
+        free(c);
+    }
+}
+
 /* Exact power-of-two rescaling of a complex number so that the larger of its
  * leading components lies in [0.5, 1); the scale goes into *E.  It changes
  * no bits of the represented value beyond the exponent, so it only protects

@@ -251,6 +251,17 @@ def polyeval_rows(mpx, torch, T):
             th = T(lambda: mpx.polyval(p, coef, x, out=y), reps=5)
             te = T(lambda: mpx.polyval(p, coef, x, out=y, method="estrin"), reps=5)
             out[f"{p}_deg{deg}"] = {"horner_us": th * 1e3, "estrin_us": te * 1e3, "estrin_speedup": th / te}
+        # the same at complex points (real coefficients; Estrin up to degree 1023)
+        for deg in (16, 64, 256, 1023):
+            coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
+            xr = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
+            xi = gpu_mp(torch, K, batch, synth.seed_for(6, 2))
+            y = (torch.empty((K, batch), dtype=torch.float64, device="cuda"),
+                 torch.empty((K, batch), dtype=torch.float64, device="cuda"))
+            th = T(lambda: mpx.polyval_cplx(p, coef, xr, xi, out=y), reps=5)
+            te = T(lambda: mpx.polyval_cplx(p, coef, xr, xi, out=y, method="estrin"), reps=5)
+            out[f"{p}_complex_deg{deg}"] = {"horner_us": th * 1e3, "estrin_us": te * 1e3,
+                                            "estrin_speedup": th / te}
     return out
 
 
@@ -295,7 +306,12 @@ def nobf_rows(mpx, torch, T):
         tb = T(lambda: mpx.polyval(bf, coef, x, out=y), reps=5)
         tn = T(lambda: mpx.polyval(nb, coef, x, out=y), reps=5)
         out[f"horner_{nb}_b{batch}_deg{deg}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb}
-        del coef, x, y
+        xi = gpu_mp(torch, K, batch, synth.seed_for(6, 2))
+        yc = (y, torch.empty_like(y))
+        tb = T(lambda: mpx.polyval_cplx(bf, coef, x, xi, out=yc), reps=5)
+        tn = T(lambda: mpx.polyval_cplx(nb, coef, x, xi, out=yc), reps=5)
+        out[f"horner_complex_{nb}_b{batch}_deg{deg}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb}
+        del coef, x, y, xi, yc
     # Durand-Kerner on the Chebyshev integration polynomial n = 64 (Table 6's
     # problem), 4096 copies in one persistent launch, Aberth start, 200 sweeps.
     from fractions import Fraction  # noqa: F401  (coefficients are exact rationals)

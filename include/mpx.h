@@ -64,8 +64,8 @@ typedef enum {
  *                 TW / QW renormalisation with data-dependent tests;
  *   MPX_NOBF_ACC  DD only: DWAccurateAdd in place of DWAdd.
  * Accepted by mpx_add, mpx_mul, mpx_axpy, mpx_dot, mpx_gemm (and its variant,
- * variant-count/name and autotune calls), mpx_gemm_strassen, mpx_polyval and
- * mpx_polyroots_plan
+ * variant-count/name and autotune calls), mpx_gemm_strassen, mpx_polyval,
+ * mpx_polyval_cplx (Horner) and mpx_polyroots_plan
  * (the plan then runs Durand-Kerner in that arithmetic); every other entry
  * point, and any flag on MPX_FF, returns MPX_EPREC.  Results of the
  * conventional operations are deterministic and meet the same error bounds
@@ -239,6 +239,21 @@ int mpx_polyval(int prec, int64_t batch, int64_t deg, const void *coef, int64_t 
  * MPX_ENOTSUP).  Same layout and errors as mpx_polyval. */
 int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
                        const void *x, int64_t psx, void *y, int64_t psy, void *stream);
+
+/* Real-coefficient polynomials at complex points (Section 4.1, the second
+ * polynomial benchmark): y_b = p_b(x_b) with coef as for mpx_polyval (real
+ * planes, batch x (deg+1)) and x, y given as real / imaginary plane sets
+ * (xre, xim share psx; yre, yim share psy).  method 0 = Horner,
+ * h = (a_n, 0), h := h x + a_i with the 4M complex product and a_i added to
+ * the real part only (arithmetic flags accepted); method 1 = Estrin's list
+ * halving, whose first level pairs real coefficients,
+ * c' = (a_2j + a_2j+1 Re x, a_2j+1 Im x), later levels c' = c_2j + c_2j+1 X
+ * with X := X^2 per level (branch-free only, deg <= 1023, else
+ * MPX_ENOTSUP).  Bit-identical to the sequential definitions; y must not
+ * alias the inputs. */
+int mpx_polyval_cplx(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
+                     const void *xre, const void *xim, int64_t psx, void *yre, void *yim,
+                     int64_t psy, int method, void *stream);
 
 /* Reverse mode of mpx_polyval for L = sum_b gy_b p_b(x_b):
  *   gcoef_{b,i} = gy_b x_b^i  (t_0 = gy_b, t_{i+1} = t_i * x_b: the adjoint of

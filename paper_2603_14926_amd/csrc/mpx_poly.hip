@@ -291,6 +291,127 @@ __device__ __forceinline__ void c_store(double* __restrict__ re, double* __restr
     mp_store<double, K>(im, ps, idx, v.im);
 }
 
+// ------------------------------------- real polynomials, complex point ----
+
+// Real-coefficient polynomial at a complex point (Section 4.1's second
+// benchmark), Horner: h = (a_n, 0); h := h z + a_i, the product in the 4M
+// form and the real coefficient added to the real part only.  One thread per
+// polynomial; AR selects branch-free or conventional operations.
+template <int K, int AR>
+__global__ void __launch_bounds__(64)
+k_polyval_cplx(long long batch, long long deg, const double* __restrict__ coef, long long psc,
+               const double* __restrict__ xre, const double* __restrict__ xim, long long psx,
+               double* __restrict__ yre, double* __restrict__ yim, long long psy) {
+    using V = mpn<double, K>;
+    const long long b = (long long)blockIdx.x * 64 + threadIdx.x;
+    if (b >= batch) return;
+    const long long off = b * (deg + 1);
+    const cplx<K> z = c_load<K>(xre, xim, psx, b);
+    cplx<K> h;
+    h.re = mp_load<double, K>(coef, psc, off + deg);
+    h.im = mp_zero<double, K>();
+    long long i = deg - 1;
+    for (; i >= 3; i -= 4) {
+        const V a0 = mp_load<double, K>(coef, psc, off + i);
+        const V a1 = mp_load<double, K>(coef, psc, off + i - 1);
+        const V a2 = mp_load<double, K>(coef, psc, off + i - 2);
+        const V a3 = mp_load<double, K>(coef, psc, off + i - 3);
+        h = c_mul<K, AR>(h, z); h.re = ar_add<AR>(h.re, a0);
+        h = c_mul<K, AR>(h, z); h.re = ar_add<AR>(h.re, a1);
+        h = c_mul<K, AR>(h, z); h.re = ar_add<AR>(h.re, a2);
+        h = c_mul<K, AR>(h, z); h.re = ar_add<AR>(h.re, a3);
+    }
+    for (; i >= 0; --i) {
+        h = c_mul<K, AR>(h, z);
+        h.re = ar_add<AR>(h.re, mp_load<double, K>(coef, psc, off + i));
+    }
+    c_store<K>(yre, yim, psy, b, h);
+}
+
+// Estrin at a complex point: the list halving of the real-argument kernel
+// (lane t owns the block of B = 2^LB coefficients from t B; the first LB
+// levels run as a lane-local binary counter, the rest across lanes).  The
+// first level pairs real coefficients, c' = (a_even + a_odd x_re,
+// a_odd x_im); later levels are complex, c' = c_even + c_odd X, and
+// X := X^2 after every level.
+template <int K, int LB, int T>
+struct EstrinCplxLocal {
+    static __device__ __forceinline__ void run(mpn<double, K>& st0, cplx<K>* st, const cplx<K>* Xl,
+                                               const double* __restrict__ coef, long long psc,
+                                               long long base, long long deg, long long off) {
+        constexpr int tz = trailing_ones(T);
+        const long long i = base + T;
+        const mpn<double, K> a = i <= deg ? mp_load<double, K>(coef, psc, off + i) : mp_zero<double, K>();
+        if constexpr (tz == 0) {
+            st0 = a;
+        } else {
+            cplx<K> cur;
+            cur.re = bf_add(st0, bf_mul(a, Xl[0].re));
+            cur.im = bf_mul(a, Xl[0].im);
+#pragma unroll
+            for (int l = 1; l < tz; ++l) cur = c_add<K>(st[l], c_mul<K>(cur, Xl[l]));
+            st[tz] = cur;
+        }
+        if constexpr ((T & 3) == 3) asm volatile("" ::: "memory");
+        EstrinCplxLocal<K, LB, T + 1>::run(st0, st, Xl, coef, psc, base, deg, off);
+    }
+};
+template <int K, int LB>
+struct EstrinCplxLocal<K, LB, (1 << LB)> {
+    static __device__ __forceinline__ void run(mpn<double, K>&, cplx<K>*, const cplx<K>*,
+                                               const double* __restrict__, long long, long long,
+                                               long long, long long) {}
+};
+
+template <int K, int LB>
+__global__ void __launch_bounds__(256)
+k_estrin_cplx(long long batch, long long deg, int L, const double* __restrict__ coef,
+              long long psc, const double* __restrict__ xre, const double* __restrict__ xim,
+              long long psx, double* __restrict__ yre, double* __restrict__ yim, long long psy) {
+    using C = cplx<K>;
+    constexpr int B = 1 << LB;
+    const long long b = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= batch) return;  // whole wave
+    const long long off = b * (deg + 1);
+    C Xl[LB + 1];
+    Xl[0] = c_load<K>(xre, xim, psx, b);
+#pragma unroll
+    for (int l = 1; l <= LB; ++l) Xl[l] = c_mul<K>(Xl[l - 1], Xl[l - 1]);
+    C c;
+    if constexpr (LB == 0) {
+        const long long i = lane;
+        c.re = i <= deg ? mp_load<double, K>(coef, psc, off + i) : mp_zero<double, K>();
+        c.im = mp_zero<double, K>();
+    } else {
+        mpn<double, K> st0;
+        C st[LB + 1];
+        EstrinCplxLocal<K, LB, 0>::run(st0, st, Xl, coef, psc, (long long)lane * B, deg, off);
+        c = st[LB];
+    }
+    C Xc = Xl[LB];
+    for (int lev = LB; lev < L; ++lev) {
+        const int sft = 1 << (lev - LB);
+        C other;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            other.re.c[q] = __shfl_down(c.re.c[q], sft, 64);
+            other.im.c[q] = __shfl_down(c.im.c[q], sft, 64);
+        }
+        C comb;
+        if (lev == 0) {  // first level with one coefficient per lane: real pairs
+            comb.re = bf_add(c.re, bf_mul(other.re, Xc.re));
+            comb.im = bf_mul(other.re, Xc.im);
+        } else {
+            comb = c_add<K>(c, c_mul<K>(other, Xc));
+        }
+        const bool leader = (lane & (2 * sft - 1)) == 0;
+        c = c_select<K>(leader, comb, c);
+        Xc = c_mul<K>(Xc, Xc);
+    }
+    if (lane == 0) c_store<K>(yre, yim, psy, b, c);
+}
+
 // ------------------------------------------------------ Durand-Kerner ----
 
 struct DkPlanDev {
@@ -583,6 +704,67 @@ static int estrin_t(long long batch, long long deg, const void* coef, long long 
         default: return MPX_ENOTSUP;
     }
 #undef MPX_ES
+    return launch_status();
+}
+
+template <int K>
+static int estrin_cplx_t(long long batch, long long deg, const void* coef, long long psc,
+                         const void* xre, const void* xim, long long psx, void* yre, void* yim,
+                         long long psy, hipStream_t s) {
+    int L = 0;
+    while ((1LL << L) < deg + 1) ++L;
+    const int LB = L > 6 ? L - 6 : 0;
+    const unsigned blocks = (unsigned)ceil_div(batch, 4);
+#define MPX_EC(LBV)                                                                            \
+    case LBV:                                                                                  \
+        k_estrin_cplx<K, LBV><<<blocks, 256, 0, s>>>(batch, deg, L, (const double*)coef, psc,  \
+                                                     (const double*)xre, (const double*)xim,   \
+                                                     psx, (double*)yre, (double*)yim, psy);    \
+        break;
+    switch (LB) {
+        MPX_EC(0) MPX_EC(1) MPX_EC(2) MPX_EC(3) MPX_EC(4)
+        default: return MPX_ENOTSUP;
+    }
+#undef MPX_EC
+    return launch_status();
+}
+
+extern "C" int mpx_polyval_cplx(int prec, int64_t batch, int64_t deg, const void* coef,
+                                int64_t psc, const void* xre, const void* xim, int64_t psx,
+                                void* yre, void* yim, int64_t psy, int method, void* stream) {
+    if (!prec_k_ar(prec) || base_prec(prec) == MPX_FF) return MPX_EPREC;
+    if (method != 0 && method != 1) return MPX_EINVAL;
+    if (method == 1 && arith_of(prec) != 0) return MPX_EPREC;
+    int st = polyval_check(base_prec(prec), batch, deg, coef, psc, xre, psx);
+    if (st) return st;
+    if (batch == 0) return MPX_OK;
+    if (xim == nullptr || yre == nullptr || yim == nullptr || psy < batch) return MPX_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (method == 1) {
+        if (deg >= 1024) return MPX_ENOTSUP;  // 16 coefficients per lane at most
+        switch (prec) {
+            case MPX_DD: return estrin_cplx_t<2>(batch, deg, coef, psc, xre, xim, psx, yre, yim, psy, s);
+            case MPX_TD: return estrin_cplx_t<3>(batch, deg, coef, psc, xre, xim, psx, yre, yim, psy, s);
+            default: return estrin_cplx_t<4>(batch, deg, coef, psc, xre, xim, psx, yre, yim, psy, s);
+        }
+    }
+    const unsigned blocks = (unsigned)ceil_div(batch, 64);
+#define MPX_PC(K_, AR_)                                                                      \
+    k_polyval_cplx<K_, AR_><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc,     \
+                                                  (const double*)xre, (const double*)xim,   \
+                                                  psx, (double*)yre, (double*)yim, psy);    \
+    break
+    switch (prec) {
+        case MPX_DD: MPX_PC(2, AR_BF);
+        case MPX_TD: MPX_PC(3, AR_BF);
+        case MPX_QD: MPX_PC(4, AR_BF);
+        case MPX_DD | MPX_NOBF: MPX_PC(2, AR_NOBF);
+        case MPX_TD | MPX_NOBF: MPX_PC(3, AR_NOBF);
+        case MPX_QD | MPX_NOBF: MPX_PC(4, AR_NOBF);
+        case MPX_DD | MPX_NOBF_ACC: MPX_PC(2, AR_NOBF_ACC);
+        default: return MPX_EPREC;
+    }
+#undef MPX_PC
     return launch_status();
 }
 

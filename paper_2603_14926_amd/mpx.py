@@ -80,6 +80,7 @@ def _declare(L):
     sig("mpx_cgemm_3m", _i, _i, _l, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _z, _v)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_estrin", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_polyval_cplx", _i, _i, _l, _l, _v, _l, _v, _v, _l, _v, _v, _l, _i, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
     sig("mpx_polyroots", _i, _v, _v, _v, _l, _v, _v, _l, _v, _v)
@@ -361,6 +362,35 @@ def polyval(p, coef, x, out=None, method="horner"):
     _check(fn(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(out), psy,
               _stream()), f"polyval ({method})")
     return out
+
+
+def polyval_cplx(p, coef, xre, xim, out=None, method="horner"):
+    """Real-coefficient polynomials at complex points: coef (K, batch, deg+1),
+    xre / xim (K, batch) -> (yre, yim) by Horner or Estrin's method."""
+    p = prec_of(p)
+    if p == FF:
+        raise ValueError("polyval_cplx supports DD / TD / QD")
+    K = ncomp(p)
+    if coef.dim() != 3 or coef.shape[0] != K:
+        raise ValueError("coef must be (K, batch, deg+1)")
+    coef = coef.contiguous()
+    psx, _ = _planes(xre, p, 1, "xre")
+    if _planes(xim, p, 1, "xim")[0] != psx or xim.shape != xre.shape:
+        raise ValueError("xim must match xre's shape and plane stride")
+    batch, d1 = coef.shape[1], coef.shape[2]
+    if xre.shape[1] != batch:
+        raise ValueError("one point per polynomial")
+    if out is None:
+        out = (torch.empty((K, batch), dtype=torch.float64, device=coef.device),
+               torch.empty((K, batch), dtype=torch.float64, device=coef.device))
+    yre, yim = out
+    psy, _ = _planes(yre, p, 1, "yre")
+    if _planes(yim, p, 1, "yim")[0] != psy:
+        raise ValueError("yim must match yre's plane stride")
+    _check(lib().mpx_polyval_cplx(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(xre), _ptr(xim),
+                                  psx, _ptr(yre), _ptr(yim), psy, {"horner": 0, "estrin": 1}[method],
+                                  _stream()), f"polyval_cplx ({method})")
+    return yre, yim
 
 
 def polyval_backward(p, coef, x, gy, want_coef=True, want_x=True):

@@ -179,3 +179,38 @@ def test_estrin_rejects_degree_beyond_2047():
     x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(mpx.MpxError):
         mpx.polyval("qd", coef, x, method="estrin")
+
+
+@pytest.mark.parametrize("p,K", PRECS)
+@pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023)])
+def test_polyval_cplx_bit_exact(p, K, batch, deg):
+    """Real-coefficient polynomials at complex points, Horner and Estrin."""
+    coef = synth.mp_array(K, (batch, deg + 1), 90 + deg, "U")
+    xr = synth.mp_array(K, batch, 91 + deg, "U")
+    xi = synth.mp_array(K, batch, 92 + deg, "U")
+    for method in ("horner", "estrin"):
+        gr, gi = mpx.polyval_cplx(p, to_gpu(coef), to_gpu(xr), to_gpu(xi), method=method)
+        wr, wi = oracle.polyval_cplx(K, coef, xr, xi, method)
+        assert bits_equal(to_np(gr), wr), (method, first_mismatch(to_np(gr), wr))
+        assert bits_equal(to_np(gi), wi), method
+
+
+@pytest.mark.parametrize("p,K,mode", [("qd_nobf", 4, "nobf"), ("td_nobf", 3, "nobf"),
+                                      ("dd_nobf_acc", 2, "nobf_acc")])
+def test_polyval_cplx_conventional_bit_exact(p, K, mode):
+    coef = synth.mp_array(K, (130, 258), 95, "U")
+    xr = synth.mp_array(K, 130, 96, "U")
+    xi = synth.mp_array(K, 130, 97, "U")
+    with oracle.arith(mode):
+        wr, wi = oracle.polyval_cplx(K, coef, xr, xi)
+    gr, gi = mpx.polyval_cplx(p, to_gpu(coef), to_gpu(xr), to_gpu(xi))
+    assert bits_equal(to_np(gr), wr) and bits_equal(to_np(gi), wi)
+
+
+def test_polyval_cplx_estrin_limits():
+    coef = torch.zeros((4, 2, 1025), dtype=torch.float64, device="cuda")
+    x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(mpx.MpxError):
+        mpx.polyval_cplx("qd", coef, x, x.clone(), method="estrin")          # degree 1024
+    with pytest.raises(mpx.MpxError):
+        mpx.polyval_cplx("qd_nobf", coef[:, :, :4].contiguous(), x, x.clone(), method="estrin")

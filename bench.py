@@ -64,8 +64,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
-                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "strassen", "durand_kerner",
-                             "autograd", "ozaki"],
+                    choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "strassen", "batched",
+                             "durand_kerner", "autograd", "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -335,6 +335,35 @@ def nobf_rows(mpx, torch, T):
     return out
 
 
+# --------------------------------------------------------- batched GEMM ----
+
+def batched_gemm_rows(mpx, torch, T):
+    """The batching pattern for small products: 4096 QD GEMMs with m, n, k
+    uniform in [16, 128] in one persistent launch (autotuned tiling), against
+    one mpx_gemm launch per problem on the same packed buffers."""
+    from paper_2603_14926_amd import synth
+    rng = np.random.default_rng(synth.seed_for(1, 50))
+    count, K = 4096, 4
+    ms, ns, ks = (rng.integers(16, 129, count) for _ in range(3))
+    plan = mpx.GemmBatchPlan("qd", ms, ns, ks)
+    a_off, b_off, c_off, (ta, tb, tc) = plan.offsets()
+    A = gpu_mp(torch, K, ta, synth.seed_for(1, 51))
+    B = gpu_mp(torch, K, tb, synth.seed_for(1, 52))
+    Cm = torch.empty((K, tc), dtype=torch.float64, device="cuda")
+    v, _ = plan.autotune(A, B, Cm, reps=1)
+    t = T(lambda: plan.run(A, B, Cm), reps=3)
+    macs = float(np.sum(ms * ns * ks))
+    views = [(A[:, a_off[i]:a_off[i] + ms[i] * ks[i]].view(K, int(ms[i]), int(ks[i])),
+              B[:, b_off[i]:b_off[i] + ks[i] * ns[i]].view(K, int(ks[i]), int(ns[i])),
+              Cm[:, c_off[i]:c_off[i] + ms[i] * ns[i]].view(K, int(ms[i]), int(ns[i])))
+             for i in range(count)]
+    tl = T(lambda: [mpx.gemm("qd", a, b, out=c) for a, b, c in views], reps=1, warmup=1)
+    return {"problems": count, "sizes": "m, n, k uniform in [16, 128]", "ms": t,
+            "mp_op_s": 2 * macs / (t * 1e-3),
+            "frac_issue_peak": macs * INSTR_PER_MAC["qd"] / (t * 1e-3) / PEAK_F64_ISSUE,
+            "variant": int(v), "per_problem_launches_ms": tl, "speedup_vs_launches": tl / t}
+
+
 # -------------------------------------------------------------- Strassen ----
 
 def strassen_rows(mpx, torch, T):
@@ -598,6 +627,7 @@ def main():
               "polyeval": lambda: polyeval_rows(mpx, torch, T),
               "nobf": lambda: nobf_rows(mpx, torch, T),
               "strassen": lambda: strassen_rows(mpx, torch, T),
+              "batched": lambda: batched_gemm_rows(mpx, torch, T),
               "durand_kerner": lambda: dk_row(mpx, torch, T),
               "autograd": lambda: autograd_row(mpx, torch, T),
               "ozaki": lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))}[args.only]
@@ -671,6 +701,7 @@ def main():
         log("horner vs estrin"); rows["polyeval"] = polyeval_rows(mpx, torch, T)
         log("bf vs nobf"); rows["bf_vs_nobf"] = nobf_rows(mpx, torch, T)
         log("strassen"); rows["strassen"] = strassen_rows(mpx, torch, T)
+        log("batched gemm"); rows["batched_gemm"] = batched_gemm_rows(mpx, torch, T)
         log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
         log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
         rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))

@@ -170,6 +170,35 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
                       int64_t psA, const void *B, int64_t ldb, int64_t psB, void *C, int64_t ldc,
                       int64_t psC, int64_t cutoff, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ batched GEMM --
+ * count independent products C_p = A_p B_p (no transposes) of ragged shapes
+ * m_p x k_p times k_p x n_p in one persistent launch: workgroups pull
+ * (problem, tile) items, longest k first, from a counter and run the tile
+ * routine of mpx_gemm, so every entry is bit-identical to mpx_gemm's (the
+ * naive triple loop's sequence).  Operands are packed per component plane:
+ * A_p starts at element sum_{q<p} m_q k_q, row-major with ld = k_p; B_p at
+ * sum_{q<p} k_q n_q (ld = n_p); C_p at sum_{q<p} m_q n_q (ld = n_p); plane
+ * strides psA / psB / psC at least the totals.  The plan (host arrays copied
+ * at creation; sizes up to 2^20 per dimension; DD, TD, QD or FF) owns a small
+ * device schedule: create and destroy it outside graph capture.
+ * mpx_gemm_batched launches two kernels (a counter reset and the persistent
+ * kernel) on the stream, allocates nothing and may be captured in a HIP
+ * graph; calls that overlap on one plan race on its counter.
+ * mpx_gemm_batched_autotune times each tiling on the caller's buffers (C is
+ * overwritten), keeps the fastest in the plan and returns its index (it
+ * synchronises the stream).  Errors as for mpx_gemm. */
+typedef struct mpx_gemm_plan_s *mpx_gemm_plan;
+int mpx_gemm_batched_plan(mpx_gemm_plan *out, int prec, int64_t count, const int64_t *m_host,
+                          const int64_t *n_host, const int64_t *k_host);
+int mpx_gemm_batched(mpx_gemm_plan plan, const void *A, int64_t psA, const void *B,
+                     int64_t psB, void *C, int64_t psC, void *stream);
+int mpx_gemm_batched_variant_count(mpx_gemm_plan plan);
+int mpx_gemm_batched_set_variant(mpx_gemm_plan plan, int variant);
+int mpx_gemm_batched_autotune(mpx_gemm_plan plan, const void *A, int64_t psA, const void *B,
+                              int64_t psB, void *C, int64_t psC, int reps, float *best_ms,
+                              void *stream);
+int mpx_gemm_plan_destroy(mpx_gemm_plan plan);
+
 /* ---------------------------------------------------------- GEMM tuning --
  * The GEMM has several register/LDS tilings ("variants"); all produce the
  * same bits.  mpx_gemm picks one per (precision, transposes, log2 size

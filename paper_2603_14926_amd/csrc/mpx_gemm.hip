@@ -31,7 +31,9 @@
 #include "mp_conv.hpp"
 #include "mpx_internal.hpp"
 
+#include <algorithm>
 #include <mutex>
+#include <new>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -40,36 +42,18 @@ namespace mpx {
 
 constexpr int kGemmThreads = 256;
 
+// One BM x BN tile of C = op(A) op(B) at (m0, n0), computed by the 256
+// threads of a workgroup with the LDS panels sA, sB (shared by k_gemm and the
+// batched kernel, so both give the same bits).
 template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR>
-__global__ void __launch_bounds__(kGemmThreads)
-k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
-       const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
-       long long ldc, long long psC, int tiles_n, int tiles_total) {
+__device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restrict__ A,
+                                          long long lda, long long psA, const T* __restrict__ B,
+                                          long long ldb, long long psB, T* __restrict__ C,
+                                          long long ldc, long long psC, int m0, int n0,
+                                          T (&sA)[K][BK][16 * TM], T (&sB)[K][BK][16 * TN]) {
     constexpr int BM = 16 * TM, BN = 16 * TN;
     constexpr int A_PER = (BM * BK + kGemmThreads - 1) / kGemmThreads;
     constexpr int B_PER = (BN * BK + kGemmThreads - 1) / kGemmThreads;
-    __shared__ T sA[K][BK][BM];
-    __shared__ T sB[K][BK][BN];
-
-    // XCD-aware tile order: workgroup w runs on XCD w % 8; each XCD gets a
-    // contiguous range of virtual tile ids, and virtual ids walk the tile grid
-    // in groups of 8 tile rows (column-major inside a group), so the
-    // workgroups resident on one XCD at a time cover a square block of C and
-    // share its A and B panels in that XCD's L2.
-    const int w = blockIdx.x;
-    const int per_xcd = (tiles_total + 7) / 8;
-    const int xcd = w % 8, slot = w / 8;
-    int v = xcd * per_xcd + slot;
-    if (per_xcd * 8 != tiles_total) v = w;  // uneven split: plain order
-    constexpr int GROUP = 8;
-    const int tiles_m = tiles_total / tiles_n;
-    const int in_group = GROUP * tiles_n;
-    const int first_m = (v / in_group) * GROUP;
-    const int rows_here = tiles_m - first_m < GROUP ? tiles_m - first_m : GROUP;
-    const int r = v % in_group;
-    const int m0 = (first_m + r % rows_here) * BM;
-    const int n0 = (r / rows_here) * BN;
-
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
 
@@ -169,6 +153,39 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
             if (cidx < n) mp_store<T, K>(C, psC, (long long)r * ldc + cidx, acc[i][j]);
         }
     }
+}
+
+
+template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
+       const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
+       long long ldc, long long psC, int tiles_n, int tiles_total) {
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    __shared__ T sA[K][BK][BM];
+    __shared__ T sB[K][BK][BN];
+
+    // XCD-aware tile order: workgroup w runs on XCD w % 8; each XCD gets a
+    // contiguous range of virtual tile ids, and virtual ids walk the tile grid
+    // in groups of 8 tile rows (column-major inside a group), so the
+    // workgroups resident on one XCD at a time cover a square block of C and
+    // share its A and B panels in that XCD's L2.
+    const int w = blockIdx.x;
+    const int per_xcd = (tiles_total + 7) / 8;
+    const int xcd = w % 8, slot = w / 8;
+    int v = xcd * per_xcd + slot;
+    if (per_xcd * 8 != tiles_total) v = w;  // uneven split: plain order
+    constexpr int GROUP = 8;
+    const int tiles_m = tiles_total / tiles_n;
+    const int in_group = GROUP * tiles_n;
+    const int first_m = (v / in_group) * GROUP;
+    const int rows_here = tiles_m - first_m < GROUP ? tiles_m - first_m : GROUP;
+    const int r = v % in_group;
+    const int m0 = (first_m + r % rows_here) * BM;
+    const int n0 = (r / rows_here) * BN;
+
+    gemm_tile<T, K, TM, TN, BK, TA, TB, AR>(m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC, m0,
+                                            n0, sA, sB);
 }
 
 // ----------------------------------------------------------- variants ----
@@ -377,4 +394,232 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
 extern "C" void mpx_gemm_autotune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+}
+
+// ------------------------------------------------------- batched GEMM ----
+//
+// Many independent products C_p = A_p B_p of ragged shapes in one persistent
+// launch (the batching pattern applied to small GEMMs).  A plan lists every
+// (problem, tile) work item of every tiling variant, longest k first; the
+// workgroups of one launch pull items from a counter and run the same tile
+// routine as k_gemm, so each entry is the naive triple loop's sequence.
+// Operands are packed: A_p (m_p x k_p, row-major) starts at element
+// sum_{q<p} m_q k_q of every component plane, likewise B_p (k_p x n_p) and
+// C_p (m_p x n_p).
+
+namespace mpx {
+
+struct GbProb {
+    int m, n, k;
+    long long a, b, c;  // first element of A_p, B_p, C_p in their planes
+};
+struct GbItem {
+    int p, m0, n0;
+};
+
+__global__ void k_gb_reset(int* c) { *c = 0; }
+
+template <typename T, int K, int TM, int TN, int BK, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm_batched(int nitems, const GbItem* __restrict__ items, const GbProb* __restrict__ probs,
+               const T* __restrict__ A, long long psA, const T* __restrict__ B, long long psB,
+               T* __restrict__ C, long long psC, int* counter) {
+    __shared__ T sA[K][BK][16 * TM];
+    __shared__ T sB[K][BK][16 * TN];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();  // all have read `next` before it is overwritten
+        if (it >= nitems) break;  // the same value in every thread: uniform exit
+        const GbItem w = items[it];
+        const GbProb q = probs[w.p];
+        gemm_tile<T, K, TM, TN, BK, false, false, AR>(q.m, q.n, q.k, A + q.a, q.k, psA, B + q.b,
+                                                      q.n, psB, C + q.c, q.n, psC, w.m0, w.n0,
+                                                      sA, sB);
+    }
+}
+
+struct GbVariant {
+    int (*launch)(int nitems, const GbItem*, const GbProb*, const void*, long long, const void*,
+                  long long, void*, long long, int*, int grid, hipStream_t);
+    int bm, bn;
+};
+
+template <typename T, int K, int TM, int TN, int BK, int AR>
+static int gb_launch(int nitems, const GbItem* items, const GbProb* probs, const void* A,
+                     long long psA, const void* B, long long psB, void* C, long long psC,
+                     int* counter, int grid, hipStream_t s) {
+    k_gemm_batched<T, K, TM, TN, BK, AR><<<grid, kGemmThreads, 0, s>>>(
+        nitems, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
+    return launch_status();
+}
+
+// Tilings offered for batches: the regular GEMM's, smallest tiles first
+// (small problems need many tiles to fill the chip).
+static std::vector<GbVariant> gb_variants(int prec) {
+#define MPX_GB(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_>, 16 * TM_, 16 * TN_}
+    switch (prec) {
+        case MPX_DD: return {MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF)};
+        case MPX_TD: return {MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
+        case MPX_QD: return {MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
+        case MPX_FF: return {MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF)};
+        default: return {};
+    }
+#undef MPX_GB
+}
+
+}  // namespace mpx
+
+struct mpx_gemm_plan_s {
+    int prec = 0, count = 0, variant = 0, cus = 256;
+    long long totA = 0, totB = 0, totC = 0;
+    std::vector<mpx::GbVariant> vars;
+    std::vector<int> nitems;           // per variant
+    std::vector<long long> item_off;   // per variant: first item in the device array
+    void* dev = nullptr;               // probs, items of every variant, counter
+    mpx::GbProb* probs = nullptr;
+    mpx::GbItem* items = nullptr;
+    int* counter = nullptr;
+};
+
+extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count,
+                                     const int64_t* m, const int64_t* n, const int64_t* k) {
+    using namespace mpx;
+    if (out == nullptr) return MPX_EINVAL;
+    *out = nullptr;
+    if (!prec_k(prec)) return MPX_EPREC;
+    if (count < 0 || count > INT32_MAX || (count > 0 && (!m || !n || !k))) return MPX_EINVAL;
+    auto* p = new (std::nothrow) mpx_gemm_plan_s();
+    if (!p) return MPX_EINVAL;
+    p->prec = prec;
+    p->count = (int)count;
+    p->vars = gb_variants(prec);
+    std::vector<GbProb> probs(count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (m[i] < 0 || n[i] < 0 || k[i] < 0 || m[i] > (1 << 20) || n[i] > (1 << 20) ||
+            k[i] > (1 << 20)) {
+            delete p;
+            return MPX_EINVAL;
+        }
+        probs[i] = GbProb{(int)m[i], (int)n[i], (int)k[i], p->totA, p->totB, p->totC};
+        p->totA += m[i] * k[i];
+        p->totB += k[i] * n[i];
+        p->totC += m[i] * n[i];
+    }
+    // work items of every variant, longest k first (ties: problem, tile order)
+    std::vector<GbItem> all;
+    for (const auto& v : p->vars) {
+        std::vector<GbItem> items;
+        for (int64_t i = 0; i < count; ++i)
+            for (int r = 0; r < probs[i].m; r += v.bm)
+                for (int c = 0; c < probs[i].n; c += v.bn) items.push_back(GbItem{(int)i, r, c});
+        std::stable_sort(items.begin(), items.end(), [&](const GbItem& a, const GbItem& b) {
+            return probs[a.p].k > probs[b.p].k;
+        });
+        p->item_off.push_back((long long)all.size());
+        p->nitems.push_back((int)items.size());
+        all.insert(all.end(), items.begin(), items.end());
+    }
+    const size_t sz_p = std::max<size_t>(probs.size(), 1) * sizeof(GbProb);
+    const size_t sz_i = std::max<size_t>(all.size(), 1) * sizeof(GbItem);
+    const size_t off_i = (sz_p + 255) & ~size_t(255), off_c = (off_i + sz_i + 255) & ~size_t(255);
+    if (hipMalloc(&p->dev, off_c + 256) != hipSuccess) {
+        delete p;
+        return MPX_EDEVICE;
+    }
+    p->probs = (GbProb*)p->dev;
+    p->items = (GbItem*)((char*)p->dev + off_i);
+    p->counter = (int*)((char*)p->dev + off_c);
+    if ((!probs.empty() && hipMemcpy(p->probs, probs.data(), probs.size() * sizeof(GbProb),
+                                     hipMemcpyHostToDevice) != hipSuccess) ||
+        (!all.empty() && hipMemcpy(p->items, all.data(), all.size() * sizeof(GbItem),
+                                   hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipFree(p->dev);
+        delete p;
+        return MPX_EDEVICE;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        p->cus = prop.multiProcessorCount;
+    *out = p;
+    return MPX_OK;
+}
+
+extern "C" int mpx_gemm_plan_destroy(mpx_gemm_plan p) {
+    if (!p) return MPX_EINVAL;
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+    return MPX_OK;
+}
+
+extern "C" int mpx_gemm_batched_variant_count(mpx_gemm_plan p) {
+    return p ? (int)p->vars.size() : 0;
+}
+
+extern "C" int mpx_gemm_batched_set_variant(mpx_gemm_plan p, int v) {
+    if (!p || v < 0 || v >= (int)p->vars.size()) return MPX_EINVAL;
+    p->variant = v;
+    return MPX_OK;
+}
+
+static int gb_check(mpx_gemm_plan p, const void* A, int64_t psA, const void* B, int64_t psB,
+                    const void* C, int64_t psC) {
+    if (!p) return MPX_EINVAL;
+    if (p->totA > 0 && (!A || psA < p->totA)) return MPX_EINVAL;
+    if (p->totB > 0 && (!B || psB < p->totB)) return MPX_EINVAL;
+    if (p->totC > 0 && (!C || psC < p->totC)) return MPX_EINVAL;
+    return MPX_OK;
+}
+
+static int gb_run(mpx_gemm_plan p, int v, const void* A, int64_t psA, const void* B,
+                  int64_t psB, void* C, int64_t psC, hipStream_t s) {
+    using namespace mpx;
+    const int ni = p->nitems[v];
+    if (ni == 0) return MPX_OK;
+    k_gb_reset<<<1, 1, 0, s>>>(p->counter);
+    int st = launch_status();
+    if (st) return st;
+    const int grid = std::min(ni, p->cus * 8);
+    return p->vars[v].launch(ni, p->items + p->item_off[v], p->probs, A, psA, B, psB, C, psC,
+                             p->counter, grid, s);
+}
+
+extern "C" int mpx_gemm_batched(mpx_gemm_plan p, const void* A, int64_t psA, const void* B,
+                                int64_t psB, void* C, int64_t psC, void* stream) {
+    int st = gb_check(p, A, psA, B, psB, C, psC);
+    if (st) return st;
+    return gb_run(p, p->variant, A, psA, B, psB, C, psC, mpx::as_stream(stream));
+}
+
+extern "C" int mpx_gemm_batched_autotune(mpx_gemm_plan p, const void* A, int64_t psA,
+                                         const void* B, int64_t psB, void* C, int64_t psC,
+                                         int reps, float* best_ms, void* stream) {
+    int st = gb_check(p, A, psA, B, psB, C, psC);
+    if (st) return st;
+    if (reps < 1) return MPX_EINVAL;
+    hipStream_t s = mpx::as_stream(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPX_EDEVICE;
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < (int)p->vars.size() && !st; ++v) {
+        if ((st = gb_run(p, v, A, psA, B, psB, C, psC, s))) break;  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !st; ++r) st = gb_run(p, v, A, psA, B, psB, C, psC, s);
+        hipEventRecord(e1, s);
+        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    p->variant = best < 0 ? 0 : best;
+    if (best_ms) *best_ms = best_t;
+    return p->variant;
 }

@@ -76,6 +76,12 @@ def _declare(L):
     sig("mpx_gemm_autotune_reset", None)
     sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
+    sig("mpx_gemm_batched_plan", _i, C.POINTER(_v), _i, _l, _v, _v, _v)
+    sig("mpx_gemm_batched", _i, _v, _v, _l, _v, _l, _v, _l, _v)
+    sig("mpx_gemm_batched_variant_count", _i, _v)
+    sig("mpx_gemm_batched_set_variant", _i, _v, _i)
+    sig("mpx_gemm_batched_autotune", _i, _v, _v, _l, _v, _l, _v, _l, _i, C.POINTER(C.c_float), _v)
+    sig("mpx_gemm_plan_destroy", _i, _v)
     sig("mpx_gemm_strassen", _i, _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _l, _v, _z, _v)
     sig("mpx_cgemm_3m", _i, _i, _l, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _v, _l, _l, _v, _z, _v)
     sig("mpx_polyval", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
@@ -311,6 +317,67 @@ def gemm_strassen(p, A, B, cutoff, out=None, ws=None):
                                    _ptr(out), max(ldc, n), psC, int(cutoff), _ptr(ws), ws.numel(),
                                    _stream()), "mpx_gemm_strassen")
     return out
+
+
+class GemmBatchPlan:
+    """Plan for many independent products C_p = A_p B_p of ragged shapes in
+    one persistent launch.  Operands are packed per component plane:
+    A is (K, sum m_p k_p), A_p row-major at offsets()[0][p], likewise B and C."""
+
+    def __init__(self, p, ms, ns, ks):
+        import numpy as np
+        self.p = prec_of(p)
+        self.ms = np.ascontiguousarray(ms, dtype=np.int64)
+        self.ns = np.ascontiguousarray(ns, dtype=np.int64)
+        self.ks = np.ascontiguousarray(ks, dtype=np.int64)
+        if not (self.ms.shape == self.ns.shape == self.ks.shape):
+            raise ValueError("ms, ns, ks must have the same length")
+        h = C.c_void_p()
+        _check(lib().mpx_gemm_batched_plan(C.byref(h), self.p, self.ms.size,
+                                           self.ms.ctypes.data_as(_v), self.ns.ctypes.data_as(_v),
+                                           self.ks.ctypes.data_as(_v)), "mpx_gemm_batched_plan")
+        self._h = h
+
+    def offsets(self):
+        """(a_off, b_off, c_off, totals) of the packed layout."""
+        import numpy as np
+        a = np.concatenate([[0], np.cumsum(self.ms * self.ks)])
+        b = np.concatenate([[0], np.cumsum(self.ks * self.ns)])
+        c = np.concatenate([[0], np.cumsum(self.ms * self.ns)])
+        return a[:-1], b[:-1], c[:-1], (int(a[-1]), int(b[-1]), int(c[-1]))
+
+    def _args(self, A, B, Cm):
+        for t, name in ((A, "A"), (B, "B"), (Cm, "C")):
+            if t.dim() != 2 or t.shape[0] != ncomp(self.p) or t.dtype != dtype_of(self.p) or not t.is_cuda:
+                raise ValueError(f"{name}: expected a (K, total) GPU tensor of the plan's precision")
+            if t.shape[1] > 1 and t.stride(1) != 1:
+                raise ValueError(f"{name}: planes must be contiguous")
+        return (_ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(Cm), Cm.stride(0))
+
+    def run(self, A, B, Cm):
+        a = self._args(A, B, Cm)
+        _check(lib().mpx_gemm_batched(self._h, *a, _stream()), "mpx_gemm_batched")
+        return Cm
+
+    def variant_count(self):
+        return int(lib().mpx_gemm_batched_variant_count(self._h))
+
+    def set_variant(self, v):
+        _check(lib().mpx_gemm_batched_set_variant(self._h, int(v)), "mpx_gemm_batched_set_variant")
+
+    def autotune(self, A, B, Cm, reps=3):
+        a = self._args(A, B, Cm)
+        best = C.c_float()
+        v = lib().mpx_gemm_batched_autotune(self._h, *a, int(reps), C.byref(best), _stream())
+        if v < 0:
+            _check(v, "mpx_gemm_batched_autotune")
+        return v, best.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.mpx_gemm_plan_destroy(h)
+            self._h = None
 
 
 def gemm_ozaki_set_variant(v: int) -> None:

@@ -99,3 +99,20 @@ def test_arithmetic_flags_accepted_only_where_declared():
         assert L.mpx_dot(p, 1, FAKE, 1, FAKE, 1, FAKE, None, 0, None) == -2
     assert L.mpx_workspace_size(1, 4 | NOBF, 1 << 20, 0, 0, 0) == \
         L.mpx_workspace_size(1, 4, 1 << 20, 0, 0, 0) > 0
+
+
+def test_batched_gemm_plan_argument_errors():
+    """Plan creation validates before touching the device."""
+    L = mpx.lib()
+    m = (C.c_int64 * 2)(4, 5)
+    h = C.c_void_p()
+    assert L.mpx_gemm_batched_plan(None, 4, 2, m, m, m) == -1
+    assert L.mpx_gemm_batched_plan(C.byref(h), 7, 2, m, m, m) == -2            # unknown precision
+    assert L.mpx_gemm_batched_plan(C.byref(h), 4 | mpx.NOBF, 2, m, m, m) == -2  # no flags here
+    assert L.mpx_gemm_batched_plan(C.byref(h), 4, -1, m, m, m) == -1
+    assert L.mpx_gemm_batched_plan(C.byref(h), 4, 2, None, m, m) == -1
+    bad = (C.c_int64 * 2)(4, -5)
+    assert L.mpx_gemm_batched_plan(C.byref(h), 4, 2, m, bad, m) == -1
+    assert L.mpx_gemm_batched(None, FAKE, 1, FAKE, 1, FAKE, 1, None) == -1
+    assert L.mpx_gemm_batched_variant_count(None) == 0
+    assert L.mpx_gemm_plan_destroy(None) == -1

@@ -68,6 +68,8 @@ def parse():
                              "durand_kerner", "autograd", "ozaki"],
                     help="measure one row only (skips the headline and the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="measure the FP64 / FP32 VALU issue rates the rooflines use, print them, exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 512 MiB read + 512 MiB write kernel (counter calibration)")
     return ap.parse_args()
@@ -619,6 +621,11 @@ def main():
     from paper_2603_14926_amd import mpx, synth
     mpx.lib()
     T = Timer(torch)
+    if args.peak_probe:
+        r = {k: mpx.probe_valu(k) for k in mpx.PROBES}
+        print(json.dumps({"peak_probe_lane_ops_per_s": r,
+                          "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE}}), flush=True)
+        return
     if args.only:
         fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd")},
               "gemv": lambda: gemv_rows(mpx, torch, T),

@@ -76,6 +76,8 @@ def _declare(L):
     sig("mpx_gemm_autotune_reset", None)
     sig("mpx_gemm_ozaki_dd", _i, _l, _l, _l, _v, _l, _l, _v, _l, _l, _v, _l, _l, _i, _i, _l, _v, _z, _v)
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
+    sig("mpx_probe_threads", _l)
+    sig("mpx_probe_valu", _i, _i, _l, _v, _l, _v)
     sig("mpx_gemm_batched_plan", _i, C.POINTER(_v), _i, _l, _v, _v, _v)
     sig("mpx_gemm_batched", _i, _v, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_gemm_batched_variant_count", _i, _v)
@@ -317,6 +319,25 @@ def gemm_strassen(p, A, B, cutoff, out=None, ws=None):
                                    _ptr(out), max(ldc, n), psC, int(cutoff), _ptr(ws), ws.numel(),
                                    _stream()), "mpx_gemm_strassen")
     return out
+
+
+PROBES = {"f64_add": 0, "f64_fma": 1, "f32_add": 2, "f32_fma": 3}
+
+
+def probe_valu(kind: str, iters: int = 1 << 12, reps: int = 3) -> float:
+    """Measured VALU issue rate (lane-operations per second) of one
+    instruction kind, from independent chains on 8 workgroups per CU."""
+    k = PROBES[kind]
+    threads = int(lib().mpx_probe_threads())
+    out = torch.empty(threads, dtype=torch.float64 if k < 2 else torch.float32, device="cuda")
+    _check(lib().mpx_probe_valu(k, iters, _ptr(out), threads, _stream()), "mpx_probe_valu")  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        _check(lib().mpx_probe_valu(k, iters, _ptr(out), threads, _stream()), "mpx_probe_valu")
+    e1.record()
+    torch.cuda.synchronize()
+    return threads * iters * 64.0 * reps / (e0.elapsed_time(e1) * 1e-3)
 
 
 class GemmBatchPlan:

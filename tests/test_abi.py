@@ -116,3 +116,11 @@ def test_batched_gemm_plan_argument_errors():
     assert L.mpx_gemm_batched(None, FAKE, 1, FAKE, 1, FAKE, 1, None) == -1
     assert L.mpx_gemm_batched_variant_count(None) == 0
     assert L.mpx_gemm_plan_destroy(None) == -1
+
+
+def test_probe_rejects_bad_arguments():
+    L = mpx.lib()
+    assert L.mpx_probe_valu(7, 1, FAKE, 256, None) == -1       # unknown kind
+    assert L.mpx_probe_valu(0, 0, FAKE, 256, None) == -1       # iters < 1
+    assert L.mpx_probe_valu(0, 1, FAKE, 300, None) == -1       # not a multiple of 256
+    assert L.mpx_probe_valu(0, 1, None, 256, None) == -1       # null output

@@ -200,8 +200,10 @@ struct GemmArgs {
 template <typename T, int K, int TM, int TN, int BK, int AR>
 static int run_variant(const GemmArgs& g, hipStream_t s) {
     constexpr int BM = 16 * TM, BN = 16 * TN;
-    const int tn = (int)ceil_div(g.n, BN), tm = (int)ceil_div(g.m, BM);
-    const int total = tn * tm;
+    const long long tiles = ceil_div(g.n, BN) * ceil_div(g.m, BM);
+    if (tiles > INT32_MAX / 2) return MPX_ENOTSUP;  // one workgroup per tile (int grid)
+    const int tn = (int)ceil_div(g.n, BN);
+    const int total = (int)tiles;
     if (total == 0) return MPX_OK;
 #define MPX_GEMM_LAUNCH(TA_, TB_)                                                           \
     k_gemm<T, K, TM, TN, BK, TA_, TB_, AR><<<total, kGemmThreads, 0, s>>>(                  \
@@ -510,6 +512,15 @@ extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count
     }
     // work items of every variant, longest k first (ties: problem, tile order)
     std::vector<GbItem> all;
+    for (const auto& v : p->vars) {
+        long long nit = 0;
+        for (int64_t i = 0; i < count; ++i)
+            nit += ceil_div(probs[i].m, v.bm) * ceil_div(probs[i].n, v.bn);
+        if (nit > INT32_MAX / 2) {  // the work counter is an int
+            delete p;
+            return MPX_ENOTSUP;
+        }
+    }
     for (const auto& v : p->vars) {
         std::vector<GbItem> items;
         for (int64_t i = 0; i < count; ++i)

@@ -24,7 +24,11 @@
  * default stream) and return before the work completes.  Argument errors are
  * detected on the host before anything is launched and nothing is written;
  * a failed launch returns MPX_EDEVICE.  No call allocates device memory
- * except mpx_polyroots_plan, and none synchronises the device.  The caller
+ * except the plan constructors (mpx_polyroots_plan, mpx_gemm_batched_plan),
+ * and none synchronises the device except the autotuners.  Sizes whose
+ * launch grid would not fit (more than 2^31 - 1 GEMV rows or columns or
+ * polynomials in a batch, more than 2^30 GEMM tiles) return MPX_ENOTSUP.
+ * The caller
  * owns every buffer; the library keeps no pointer after a call returns
  * (plans keep the buffers they are given, see below).  Inputs are assumed
  * finite and normal (Section 2); NaN / Inf / subnormal handling is
@@ -32,9 +36,10 @@
  * equal x or y) and mpx_axpy (y in place).
  *
  * Determinism: every call is bitwise reproducible for the same arguments.
- * Elementwise ops, AXPY, GEMM, Horner and the root solver perform, per
- * output, exactly the operation sequence of the sequential definition, so
- * their results do not depend on tile sizes or launch configuration.  Dot
+ * Elementwise ops, AXPY, GEMM (plain, batched, Strassen, 3M), Horner,
+ * Estrin and the root solver perform, per output, exactly the operation
+ * sequence of their sequential definition, so their results do not depend
+ * on tile sizes or launch configuration.  Dot
  * and GEMV combine partial sums in a fixed tree whose shape depends only on
  * the problem size.
  */

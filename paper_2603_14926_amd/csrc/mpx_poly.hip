@@ -655,6 +655,7 @@ static int polyval_check(int prec, int64_t batch, int64_t deg, const void* coef,
                          const void* x, int64_t psx) {
     if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
     if (batch < 0 || deg < 0) return MPX_EINVAL;
+    if (batch > INT32_MAX) return MPX_ENOTSUP;  // grid dimensions
     if (batch == 0) return MPX_OK;
     if (coef == nullptr || psc < batch * (deg + 1) || x == nullptr || psx < batch) return MPX_EINVAL;
     return MPX_OK;

@@ -396,6 +396,7 @@ extern "C" int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void* A
                         size_t ws_bytes, void* stream) {
     if (!prec_k(prec)) return MPX_EPREC;
     if (m < 0 || n < 0 || (trans != 0 && trans != 1)) return MPX_EINVAL;
+    if (m > INT32_MAX || n > INT32_MAX) return MPX_ENOTSUP;  // grid dimensions
     const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
     if (m > 0 && n > 0 && (A == nullptr || lda < n || psA < (m - 1) * lda + n)) return MPX_EINVAL;
     int st;

@@ -24,8 +24,9 @@
  * default stream) and return before the work completes.  Argument errors are
  * detected on the host before anything is launched and nothing is written;
  * a failed launch returns MPX_EDEVICE.  No call allocates device memory
- * except the plan constructors (mpx_polyroots_plan, mpx_gemm_batched_plan),
- * and none synchronises the device except the autotuners.  Sizes whose
+ * except the plan constructors (mpx_polyroots_plan, mpx_gemm_batched_plan)
+ * and mpx_polyroots_autotune (a scratch copy of the roots), and none
+ * synchronises the device except the autotuners.  Sizes whose
  * launch grid would not fit (more than 2^31 - 1 GEMV rows or columns or
  * polynomials in a batch, more than 2^30 GEMM tiles) return MPX_ENOTSUP.
  * The caller

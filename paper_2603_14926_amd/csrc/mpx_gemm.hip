@@ -365,24 +365,20 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
     if (m == 0 || n == 0 || reps < 1) return MPX_EINVAL;
     GemmArgs g{(int)m, (int)n, (int)k, transA, transB, A, lda, psA, B, ldb, psB, C, ldc, psC};
     hipStream_t s = as_stream(stream);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPX_EDEVICE;
+    EventPair ev;
+    if (!ev.ok) return MPX_EDEVICE;
     const auto& vs = variants(prec);
     int best = -1;
     float best_t = 0.f;
     for (int v = 0; v < (int)vs.size(); ++v) {
         if ((st = vs[v].fn(g, s))) break;  // warm-up
-        hipEventRecord(e0, s);
+        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
         for (int r = 0; r < reps && !st; ++r) st = vs[v].fn(g, s);
-        hipEventRecord(e1, s);
-        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
         ms /= reps;
         if (best < 0 || ms < best_t) { best = v; best_t = ms; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     if (st) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -612,23 +608,19 @@ extern "C" int mpx_gemm_batched_autotune(mpx_gemm_plan p, const void* A, int64_t
     if (st) return st;
     if (reps < 1) return MPX_EINVAL;
     hipStream_t s = mpx::as_stream(stream);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPX_EDEVICE;
+    mpx::EventPair ev;
+    if (!ev.ok) return MPX_EDEVICE;
     int best = -1;
     float best_t = 0.f;
     for (int v = 0; v < (int)p->vars.size() && !st; ++v) {
         if ((st = gb_run(p, v, A, psA, B, psB, C, psC, s))) break;  // warm-up
-        hipEventRecord(e0, s);
+        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
         for (int r = 0; r < reps && !st; ++r) st = gb_run(p, v, A, psA, B, psB, C, psC, s);
-        hipEventRecord(e1, s);
-        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
         ms /= reps;
         if (best < 0 || ms < best_t) { best = v; best_t = ms; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     if (st) return st;
     p->variant = best < 0 ? 0 : best;
     if (best_ms) *best_ms = best_t;

@@ -50,6 +50,26 @@ inline int launch_status() {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Two HIP events bracketing timed work on a stream (the autotuners); both are
+// destroyed on scope exit.  Every step reports failure instead of ignoring it.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool ok = false;
+    EventPair() { ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    bool start(hipStream_t s) { return hipEventRecord(a, s) == hipSuccess; }
+    bool stop(hipStream_t s) { return hipEventRecord(b, s) == hipSuccess; }
+    // Waits for the stop event; milliseconds between the two.
+    bool elapsed(float* ms) {
+        return hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(ms, a, b) == hipSuccess;
+    }
+};
+
 }  // namespace mpx
 
 namespace mpx {

@@ -873,7 +873,7 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     }
     if (e == hipSuccess) e = hipMemcpy(d_coff, coff.data(), sz_off, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_roff, roff.data(), sz_off, hipMemcpyHostToDevice);
-    if (e != hipSuccess) { hipFree(p->dev); delete p; return MPX_EDEVICE; }
+    if (e != hipSuccess) { (void)hipFree(p->dev); delete p; return MPX_EDEVICE; }
     const long long psm = std::max<long long>(p->total_coef, 1);
     const long long psz = std::max<long long>(p->total_roots, 1);
     p->d = DkPlanDev{d_order, d_deg, d_coff, d_roff, d_m, d_m + K * psm, d_z, d_z + K * psz,
@@ -884,9 +884,9 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
 
 extern "C" int mpx_plan_destroy(mpx_plan p) {
     if (!p) return MPX_OK;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->dev) hipFree(p->dev);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->dev) (void)hipFree(p->dev);
     delete p;
     return MPX_OK;
 }
@@ -915,15 +915,15 @@ extern "C" int mpx_polyroots(mpx_plan p, const void* coef_re, const void* coef_i
                 p->g_ps[1] == psr;
     for (int i = 0; i < 6 && same; ++i) same = key[i] == p->g_key[i];
     if (!same) {
-        if (p->exec) { hipGraphExecDestroy(p->exec); p->exec = nullptr; }
-        if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPX_EDEVICE;
         st = launch_dk(p, p->variant, coef_re, coef_im, psc, roots_re, roots_im, psr, status, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
-        if (st || e != hipSuccess) { if (g) hipGraphDestroy(g); return st ? st : MPX_EDEVICE; }
+        if (st || e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return st ? st : MPX_EDEVICE; }
         if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             return MPX_EDEVICE;
         }
         p->graph = g;
@@ -960,9 +960,11 @@ extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const voi
     if (hipMalloc(&tmp, 2 * p->K * plane) != hipSuccess) return MPX_EDEVICE;
     double* tre = tmp;
     double* tim = tmp + (size_t)p->K * p->total_roots;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    EventPair ev;
+    if (!ev.ok) {
+        (void)hipFree(tmp);
+        return MPX_EDEVICE;
+    }
     const int saved_iters = p->iters;
     const unsigned saved_flags = p->flags;
     p->iters = iters_probe;
@@ -978,19 +980,16 @@ extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const voi
                 st = MPX_EDEVICE;
         }
         if (st) break;
-        hipEventRecord(e0, s);
+        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
         st = launch_dk(p, v, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);
-        hipEventRecord(e1, s);
-        if (st || hipEventSynchronize(e1) != hipSuccess) { st = st ? st : MPX_EDEVICE; break; }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
         if (best < 0 || ms < best_t) { best = v; best_t = ms; }
     }
     p->iters = saved_iters;
     p->flags = saved_flags;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(tmp);
+    if (hipStreamSynchronize(s) != hipSuccess && !st) st = MPX_EDEVICE;  // before freeing tmp
+    (void)hipFree(tmp);
     if (st) return st;
     p->variant = best;
     if (best_ms) *best_ms = best_t;

@@ -233,10 +233,12 @@ void mpx_gemm_autotune_reset(void);
  * Ozaki-style error-free split evaluated on the FP64 matrix cores.  The
  * paper lists the Ozaki scheme among its GEMM schemes (Section 3.1) without
  * defining it; the reading implemented:
- *   e_i: max_l |A_il[0]| < 2^{e_i} (0 for a zero row); f_j likewise for the
- *        columns of B;
+ *   e_ib: for k-block b (kblk consecutive k indices) of row i of A,
+ *        max_{l in b} |A_il[0]| < 2^{e_ib} (0 for a zero block); f_jb likewise
+ *        for the k-blocks of the columns of B;
  *   slices: for p = 1..slices, m_p = rint(r1 * 2^{p*beta - e}),
- *        (r1, r2) := TwoSum(r1 - m_p 2^{e - p*beta}, r2), from (hi, lo);
+ *        (r1, r2) := TwoSum(r1 - m_p 2^{e - p*beta}, r2), from (hi, lo), e
+ *        the exponent of the element's block;
  *   level sums over k-blocks of kblk: S_g = sum_{p+q=g} sum_l mA_p mB_q,
  *        g = 2..slices+1, exact in binary64: |m_1| <= 2^beta and
  *        |m_p| <= 2^(beta-1) (p >= 2) bound |S_g| by
@@ -244,11 +246,11 @@ void mpx_gemm_autotune_reset(void);
  *        (else MPX_EINVAL; e.g. beta = 22 with kblk = 256 allows 6 slices,
  *        beta = 20 with kblk = 256 allows 12);
  *   C_ij = DWBFAdd accumulation (k-blocks ascending, g ascending) of
- *        (S_g 2^{e_i + f_j - g beta}, 0).
+ *        (S_g 2^{e_ib + f_jb - g beta}, 0) of block b.
  * slices in 1..12, kblk a positive multiple of 16.  The result is
  * independent of the tiling and stage depth (bit-reproducible).  ws:
  * mpx_workspace_size(MPX_OP_OZAKI, MPX_DD, m, n, k, slices) bytes (the slice
- * planes of A and B). */
+ * planes of A and B and the block exponents; the size holds for every kblk). */
 int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
                       int64_t psA, const double *B, int64_t ldb, int64_t psB, double *C,
                       int64_t ldc, int64_t psC, int slices, int beta, int64_t kblk, void *ws,

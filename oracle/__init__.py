@@ -415,25 +415,29 @@ def polyroots(K, degrees, coef_re, coef_im, roots_re=None, roots_im=None, iters=
 
 # ------------------------------------------------------------------ Ozaki ----
 
-def ozaki_split_rows(A, s, beta):
-    """Row exponents (m,) and integer slices (s, m, k) of a DD matrix (2, m, k)."""
+def ozaki_split_rows(A, s, beta, kblk):
+    """Block exponents (m, nb) -- one per row and k-block of kblk columns --
+    and integer slices (s, m, k) of a DD matrix (2, m, k)."""
     A = _chk(A, 2)
     m, k = A.shape[1], A.shape[2]
-    e = np.zeros(m, np.int32)
+    nb = -(-k // kblk)
+    e = np.zeros((m, nb), np.int32)
     sl = np.zeros((s, m, k))
     lib().orc_ozaki_split_rows(_i64(m), _i64(k), _p(A), _i64(k), _i64(m * k), _i32(s),
-                               _i32(beta), _p(e), _p(sl))
+                               _i32(beta), _i64(kblk), _p(e), _p(sl))
     return e, sl
 
 
-def ozaki_split_cols(B, s, beta):
-    """Column exponents (n,) and integer slices (s, k, n) of a DD matrix (2, k, n)."""
+def ozaki_split_cols(B, s, beta, kblk):
+    """Block exponents (n, nb) -- one per column and k-block of kblk rows --
+    and integer slices (s, k, n) of a DD matrix (2, k, n)."""
     B = _chk(B, 2)
     k, n = B.shape[1], B.shape[2]
-    f = np.zeros(n, np.int32)
+    nb = -(-k // kblk)
+    f = np.zeros((n, nb), np.int32)
     sl = np.zeros((s, k, n))
     lib().orc_ozaki_split_cols(_i64(k), _i64(n), _p(B), _i64(n), _i64(k * n), _i32(s),
-                               _i32(beta), _p(f), _p(sl))
+                               _i32(beta), _i64(kblk), _p(f), _p(sl))
     return f, sl
 
 
@@ -449,8 +453,8 @@ def ozaki_entries(A, B, rows, cols, s, beta, kblk):
     Bs = np.ascontiguousarray(B[:, :, uc])
     m, k = As.shape[1], As.shape[2]
     n = Bs.shape[2]
-    e, sa = ozaki_split_rows(As, s, beta)
-    f, sb = ozaki_split_cols(Bs, s, beta)
+    e, sa = ozaki_split_rows(As, s, beta, kblk)
+    f, sb = ozaki_split_cols(Bs, s, beta, kblk)
     r2 = np.ascontiguousarray(ri.astype(np.int64)); c2 = np.ascontiguousarray(ci.astype(np.int64))
     out = np.zeros((2, rows.size))
     lib().orc_ozaki_entries(_i64(m), _i64(n), _i64(k), _i32(s), _i32(beta), _i64(kblk),

@@ -1166,19 +1166,21 @@ void orc_dk_horner(int K, int64_t n, const double *cre, const double *cim, int64
 /* Ozaki-style error-free splitting of DD matrices and the slice GEMM.       */
 /* The paper only names the Ozaki scheme among its GEMM schemes (Section     */
 /* 3.1); the reading implemented here:                                       */
-/*  * row i of A gets the exponent e_i with max_l |A_il[0]| < 2^{e_i}        */
-/*    (frexp of the maximum; e_i = 0 for an all-zero row); column j of B     */
-/*    gets f_j the same way;                                                 */
+/*  * each k-block b (kblk consecutive k indices) of row i of A gets the     */
+/*    exponent e_ib with max over the block of |A_il[0]| < 2^{e_ib} (frexp   */
+/*    of the maximum; 0 for an all-zero block); each k-block of column j of  */
+/*    B gets f_jb the same way;                                              */
 /*  * slice p = 1..s of an element (r1, r2) = (hi, lo) is the integer        */
-/*    m_p = rint(r1 * 2^{p*beta - e}), then (r1, r2) := TwoSum(r1 - m_p *    */
-/*    2^{e - p*beta}, r2): the residual stays exact;                          */
+/*    m_p = rint(r1 * 2^{p*beta - e}), e its block's exponent, then          */
+/*    (r1, r2) := TwoSum(r1 - m_p 2^{e - p*beta}, r2): the residual stays    */
+/*    exact;                                                                 */
 /*  * level g = p + q collects sum_{p+q=g} sum_{l in block} mA_p mB_q in one */
 /*    binary64 accumulator, exact because every term is an integer and, with */
 /*    |m_1| <= 2^beta, |m_p| <= 2^(beta-1) for p >= 2, every partial sum is  */
 /*    at most kblk 2^{2 beta} (1 + max(0, s-2)/4) <= 2^53 (the caller's      */
 /*    parameter choice; the tests check it);                                 */
-/*  * C_ij = sum over k-blocks (ascending), levels g = 2..s+1 (ascending) of */
-/*    DWBFAdd(acc, (S_g * 2^{e_i + f_j - g*beta}, 0)).                       */
+/*  * C_ij = sum over k-blocks b (ascending), levels g = 2..s+1 (ascending)  */
+/*    of DWBFAdd(acc, (S_g * 2^{e_ib + f_jb - g*beta}, 0)).                  */
 /* ------------------------------------------------------------------------ */
 
 static int exp_of_max(double m) {
@@ -1199,37 +1201,46 @@ static void split_value(double hi, double lo, int e, int s, int beta, double *m)
     }
 }
 
-/* Row exponents and slices of A (m x k, row-major, DD planes): slices are
- * written as s planes of m x k (plane stride m*k). */
+/* Block exponents and slices of A (m x k, row-major, DD planes): e_row is
+ * m x nb (nb = ceil(k / kblk), row-major), slices are s planes of m x k
+ * (plane stride m*k). */
 void orc_ozaki_split_rows(int64_t m, int64_t k, const double *A, int64_t lda,
-                          int64_t psA, int s, int beta, int32_t *e_row,
+                          int64_t psA, int s, int beta, int64_t kblk, int32_t *e_row,
                           double *slices) {
+    const int64_t nb = (k + kblk - 1) / kblk;
     for (int64_t i = 0; i < m; i++) {
-        double mx = 0.0;
-        for (int64_t l = 0; l < k; l++) mx = fmax(mx, fabs(A[i * lda + l]));
-        int e = exp_of_max(mx);
-        e_row[i] = e;
-        for (int64_t l = 0; l < k; l++) {
-            double sl[64];
-            split_value(A[i * lda + l], A[psA + i * lda + l], e, s, beta, sl);
-            for (int p = 0; p < s; p++) slices[(int64_t)p * m * k + i * k + l] = sl[p];
+        for (int64_t b = 0; b < nb; b++) {
+            const int64_t l0 = b * kblk, l1 = l0 + kblk < k ? l0 + kblk : k;
+            double mx = 0.0;
+            for (int64_t l = l0; l < l1; l++) mx = fmax(mx, fabs(A[i * lda + l]));
+            int e = exp_of_max(mx);
+            e_row[i * nb + b] = e;
+            for (int64_t l = l0; l < l1; l++) {
+                double sl[64];
+                split_value(A[i * lda + l], A[psA + i * lda + l], e, s, beta, sl);
+                for (int p = 0; p < s; p++) slices[(int64_t)p * m * k + i * k + l] = sl[p];
+            }
         }
     }
 }
-/* Column exponents and slices of B (k x n, row-major, DD planes): s planes of
- * k x n. */
+/* Block exponents and slices of B (k x n, row-major, DD planes): f_col is
+ * n x nb (row-major), slices are s planes of k x n. */
 void orc_ozaki_split_cols(int64_t k, int64_t n, const double *B, int64_t ldb,
-                          int64_t psB, int s, int beta, int32_t *f_col,
+                          int64_t psB, int s, int beta, int64_t kblk, int32_t *f_col,
                           double *slices) {
+    const int64_t nb = (k + kblk - 1) / kblk;
     for (int64_t j = 0; j < n; j++) {
-        double mx = 0.0;
-        for (int64_t l = 0; l < k; l++) mx = fmax(mx, fabs(B[l * ldb + j]));
-        int f = exp_of_max(mx);
-        f_col[j] = f;
-        for (int64_t l = 0; l < k; l++) {
-            double sl[64];
-            split_value(B[l * ldb + j], B[psB + l * ldb + j], f, s, beta, sl);
-            for (int p = 0; p < s; p++) slices[(int64_t)p * k * n + l * n + j] = sl[p];
+        for (int64_t b = 0; b < nb; b++) {
+            const int64_t l0 = b * kblk, l1 = l0 + kblk < k ? l0 + kblk : k;
+            double mx = 0.0;
+            for (int64_t l = l0; l < l1; l++) mx = fmax(mx, fabs(B[l * ldb + j]));
+            int f = exp_of_max(mx);
+            f_col[j * nb + b] = f;
+            for (int64_t l = l0; l < l1; l++) {
+                double sl[64];
+                split_value(B[l * ldb + j], B[psB + l * ldb + j], f, s, beta, sl);
+                for (int p = 0; p < s; p++) slices[(int64_t)p * k * n + l * n + j] = sl[p];
+            }
         }
     }
 }
@@ -1242,9 +1253,11 @@ void orc_ozaki_entries(int64_t m, int64_t n, int64_t k, int s, int beta, int64_t
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < cnt; t++) {
         int64_t i = rows[t], j = cols[t];
+        const int64_t nb = (k + kblk - 1) / kblk;
         double acc[2] = {0.0, 0.0};
         for (int64_t l0 = 0; l0 < k; l0 += kblk) {
             int64_t l1 = l0 + kblk < k ? l0 + kblk : k;
+            const int64_t b = l0 / kblk;
             for (int g = 2; g <= s + 1; g++) {
                 double S = 0.0;
                 for (int p = 1; p < g; p++) {
@@ -1254,7 +1267,7 @@ void orc_ozaki_entries(int64_t m, int64_t n, int64_t k, int s, int beta, int64_t
                         S += sa[(int64_t)(p - 1) * m * k + i * k + l] *
                              sb[(int64_t)(q - 1) * k * n + l * n + j];
                 }
-                double term[2] = {ldexp(S, e_row[i] + f_col[j] - g * beta), 0.0};
+                double term[2] = {ldexp(S, e_row[i * nb + b] + f_col[j * nb + b] - g * beta), 0.0};
                 dw_bf_add(acc, term, acc);
             }
         }

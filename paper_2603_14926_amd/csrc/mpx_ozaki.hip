@@ -4,17 +4,20 @@
 // library without giving it; this is the reading implemented (the CPU
 // reference implements the same definition independently):
 //
-//  1. exponents: e_i with max_l |A_il.hi| < 2^{e_i} (frexp of the row
-//     maximum; 0 for a zero row), f_j likewise for the columns of B;
+//  1. exponents per k-block b of kblk consecutive k: e_ib with
+//     max_{l in b} |A_il.hi| < 2^{e_ib} (frexp of the block maximum; 0 for a
+//     zero block), f_jb likewise for the columns of B; a block of small
+//     entries is so split relative to its own size, not to the row's;
 //  2. error-free split of each DD element (hi, lo) into s integer slices:
 //     m_p = rint(r1 * 2^{p beta - e}), then (r1, r2) := TwoSum(r1 - m_p
-//     2^{e - p beta}, r2), p = 1..s, starting from (r1, r2) = (hi, lo);
+//     2^{e - p beta}, r2), p = 1..s, starting from (r1, r2) = (hi, lo), e
+//     the exponent of the element's block;
 //  3. for each k-block of kblk columns and each level g = p + q
 //     (2 <= g <= s + 1) the level sum S_g = sum_{p+q=g} sum_l mA_p mB_q is
 //     an integer below 2^53 (kblk (g-1) 2^{2 beta} < 2^53), so binary64
 //     accumulation is exact in any order -- here the MFMA units compute it;
 //  4. C_ij = DWBFAdd-accumulation, k-blocks ascending and g ascending, of
-//     (S_g 2^{e_i + f_j - g beta}, 0).
+//     (S_g 2^{e_ib + f_jb - g beta}, 0).
 //
 // Kernels: row / column maxima, the split (VALU, HBM-bound, writes the s
 // integer slice planes of A and B zero-padded to the tile grid), and the
@@ -42,29 +45,39 @@ __device__ __forceinline__ int exp_of(double m) {
     return m == 0.0 ? 0 : __builtin_amdgcn_frexp_exp(m);  // m = f 2^e, 0.5 <= f < 1
 }
 
-// e_i for row i of A (hi plane): one wave per row.
+// Block exponents are stored block-major: e[b * mp + i], f[b * np + j], so
+// the fold of block b reads one contiguous run of each.
+
+// e_ib for row i of A (hi plane): one wave per row, blocks in turn.
 __global__ void __launch_bounds__(256)
 k_oz_row_exp(long long m, long long k, const double* __restrict__ A, long long lda,
-             int* __restrict__ e) {
+             long long kblk, int* __restrict__ e, long long mp) {
     const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
-    double mx = 0.0;
-    for (long long l = lane; l < k; l += 64) mx = fmax(mx, fabs(A[row * lda + l]));
+    for (long long l0 = 0, b = 0; l0 < k; l0 += kblk, ++b) {
+        const long long l1 = l0 + kblk < k ? l0 + kblk : k;
+        double mx = 0.0;
+        for (long long l = l0 + lane; l < l1; l += 64) mx = fmax(mx, fabs(A[row * lda + l]));
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (lane == 0) e[row] = exp_of(mx);
+        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (lane == 0) e[b * mp + row] = exp_of(mx);
+    }
 }
 
-// f_j for column j of B (hi plane): one thread per column, rows sequential.
+// f_jb for column j of B (hi plane): one thread per (column, block), the
+// block's rows in turn; grid.y strides over the nb blocks.
 __global__ void __launch_bounds__(256)
 k_oz_col_exp(long long k, long long n, const double* __restrict__ B, long long ldb,
-             int* __restrict__ f) {
+             long long kblk, long long nb, int* __restrict__ f, long long np) {
     const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
-    double mx = 0.0;
-    for (long long l = 0; l < k; ++l) mx = fmax(mx, fabs(B[l * ldb + j]));
-    f[j] = exp_of(mx);
+    for (long long b = blockIdx.y; b < nb; b += gridDim.y) {
+        const long long l0 = b * kblk, l1 = l0 + kblk < k ? l0 + kblk : k;
+        double mx = 0.0;
+        for (long long l = l0; l < l1; ++l) mx = fmax(mx, fabs(B[l * ldb + j]));
+        f[b * np + j] = exp_of(mx);
+    }
 }
 
 // Split one DD value into s integer slices (step 2 above).
@@ -86,15 +99,15 @@ __device__ __forceinline__ void split_dd(double hi, double lo, int e, int beta, 
 template <int S>
 __global__ void __launch_bounds__(256)
 k_oz_split_a(long long m, long long k, const double* __restrict__ A, long long lda,
-             long long psA, const int* __restrict__ e, int beta, double* __restrict__ SA,
-             long long mp, long long kp) {
+             long long psA, const int* __restrict__ e, long long kblk, int beta,
+             double* __restrict__ SA, long long mp, long long kp) {
     const long long total = mp * kp;
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total;
          t += (long long)gridDim.x * 256) {
         const long long l = t / mp, i = t % mp;
         double sl[S];
         if (i < m && l < k) {
-            split_dd<S>(A[i * lda + l], A[psA + i * lda + l], e[i], beta, sl);
+            split_dd<S>(A[i * lda + l], A[psA + i * lda + l], e[(l / kblk) * mp + i], beta, sl);
         } else {
 #pragma unroll
             for (int p = 0; p < S; ++p) sl[p] = 0.0;
@@ -107,15 +120,15 @@ k_oz_split_a(long long m, long long k, const double* __restrict__ A, long long l
 template <int S>
 __global__ void __launch_bounds__(256)
 k_oz_split_b(long long k, long long n, const double* __restrict__ B, long long ldb,
-             long long psB, const int* __restrict__ f, int beta, double* __restrict__ SB,
-             long long kp, long long np) {
+             long long psB, const int* __restrict__ f, long long kblk, int beta,
+             double* __restrict__ SB, long long kp, long long np) {
     const long long total = kp * np;
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total;
          t += (long long)gridDim.x * 256) {
         const long long l = t / np, j = t % np;
         double sl[S];
         if (l < k && j < n) {
-            split_dd<S>(B[l * ldb + j], B[psB + l * ldb + j], f[j], beta, sl);
+            split_dd<S>(B[l * ldb + j], B[psB + l * ldb + j], f[(l / kblk) * np + j], beta, sl);
         } else {
 #pragma unroll
             for (int p = 0; p < S; ++p) sl[p] = 0.0;
@@ -215,17 +228,20 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
         for (int it = 0; it < B_V2; ++it)
             *reinterpret_cast<d2_t*>(&sB[0][0][0] + ob[it]) = rb[it];
     };
-    auto fold = [&]() __attribute__((always_inline)) {
+    // fold of k-block blk: its level sums scaled by that block's exponents
+    auto fold = [&](long long blk) __attribute__((always_inline)) {
+        const int* __restrict__ eb = e + blk * mp;
+        const int* __restrict__ fb = f + blk * np;
 #pragma unroll
         for (int a = 0; a < TA; ++a)
 #pragma unroll
             for (int b = 0; b < TB; ++b) {
                 const long long j = n0 + wc + 16 * b + lr;
-                const int fj = j < n ? f[j] : 0;
+                const int fj = j < n ? fb[j] : 0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const long long i = m0 + wr + 16 * a + lk + 4 * v;
-                    const int ei = i < m ? e[i] : 0;
+                    const int ei = i < m ? eb[i] : 0;
 #pragma unroll
                     for (int g = 0; g < S; ++g) {
                         mpn<double, 2> t;
@@ -242,7 +258,7 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
     if (kp > 0) fetch(0);
     // k-blocks [0, kblk), [kblk, 2 kblk), ... (the padded tail beyond k holds
     // zero slices); the level sums are folded once per block.
-    for (long long kb = 0; kb < kp; kb += kblk) {
+    for (long long kb = 0, blk = 0; kb < kp; kb += kblk, ++blk) {
         const long long kend = kb + kblk < kp ? kb + kblk : kp;
         for (long long kc = kb; kc < kend; kc += OZ_KT) {
             __syncthreads();  // previous stage consumed
@@ -276,7 +292,7 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
                 }
             }
         }
-        fold();
+        fold(blk);
     }
 #pragma unroll
     for (int a = 0; a < TA; ++a)
@@ -312,11 +328,14 @@ static OzDims oz_dims(long long m, long long n, long long k) {
     return {ceil_div(m, OZ_BM) * OZ_BM, ceil_div(n, OZ_BN) * OZ_BN, ceil_div(k, OZ_KPAD) * OZ_KPAD};
 }
 
+// Block exponents are sized for the smallest block (kblk = 16), so the size
+// does not depend on kblk: at most kp / 16 blocks.
 size_t ozaki_workspace(long long m, long long n, long long k, int slices) {
     if (slices < 1 || slices > OZ_MAX_S) return 0;
     const OzDims d = oz_dims(m, n, k);
     const size_t sl = (size_t)slices * (size_t)(d.mp * d.kp + d.kp * d.np) * sizeof(double);
-    return sl + (size_t)(d.mp + d.np) * sizeof(int) + 512;
+    const size_t nb_max = (size_t)(d.kp / OZ_KPAD);
+    return sl + nb_max * (size_t)(d.mp + d.np) * sizeof(int) + 512;
 }
 
 template <int S>
@@ -330,21 +349,26 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     p += (size_t)S * d.mp * d.kp * sizeof(double);
     double* SB = (double*)p;
     p += (size_t)S * d.kp * d.np * sizeof(double);
-    int* e = (int*)p;
-    int* f = e + d.mp;
+    const long long nb = ceil_div(k, kblk);  // == ceil(kp / kblk): kblk is a multiple of 16
+    int* e = (int*)p;                         // nb x mp, block-major
+    int* f = e + nb * d.mp;                   // nb x np
     int st;
-    k_oz_row_exp<<<(unsigned)ceil_div(m, 4), 256, 0, s>>>(m, k, A, lda, e);
-    if ((st = launch_status())) return st;
-    k_oz_col_exp<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(k, n, B, ldb, f);
-    if ((st = launch_status())) return st;
+    if (k > 0) {
+        k_oz_row_exp<<<(unsigned)ceil_div(m, 4), 256, 0, s>>>(m, k, A, lda, kblk, e, d.mp);
+        if ((st = launch_status())) return st;
+        const unsigned gy = (unsigned)std::min<long long>(nb, 65535);
+        k_oz_col_exp<<<dim3((unsigned)ceil_div(n, 256), gy), 256, 0, s>>>(k, n, B, ldb, kblk, nb, f,
+                                                                          d.np);
+        if ((st = launch_status())) return st;
+    }
     const long long ta = d.mp * d.kp, tb = d.kp * d.np;
     if (ta > 0)
     k_oz_split_a<S><<<(unsigned)std::min<long long>(ceil_div(ta, 256), 65536), 256, 0, s>>>(
-        m, k, A, lda, psA, e, beta, SA, d.mp, d.kp);
+        m, k, A, lda, psA, e, kblk, beta, SA, d.mp, d.kp);
     if ((st = launch_status())) return st;
     if (tb > 0)
     k_oz_split_b<S><<<(unsigned)std::min<long long>(ceil_div(tb, 256), 65536), 256, 0, s>>>(
-        k, n, B, ldb, psB, f, beta, SB, d.kp, d.np);
+        k, n, B, ldb, psB, f, kblk, beta, SB, d.kp, d.np);
     if ((st = launch_status())) return st;
     constexpr int TA = oz_ta(S);
     const int tn = (int)(d.np / 32), tm = (int)(d.mp / (32 * TA));

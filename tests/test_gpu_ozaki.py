@@ -67,3 +67,20 @@ def test_ozaki_wider_slices_smaller_blocks_bit_exact(s, beta, kblk):
     rows, cols = np.divmod(np.arange(m * n), n)
     want = oracle.ozaki_entries(A, B, rows, cols, s=s, beta=beta, kblk=kblk).reshape(2, m, n)
     assert bits_equal(got, want), first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("kblk,k", [(16, 200), (48, 130), (32, 32)])
+def test_ozaki_block_exponents_bit_exact(kblk, k):
+    """k-blocks of very different magnitude (each gets its own exponents), a
+    zero block, and a ragged last block: bit-exact against the oracle."""
+    m, n = 37, 70
+    A = synth.mp_array(2, (m, k), 900 + k, "W", phi=2.0)
+    B = synth.mp_array(2, (k, n), 901 + k, "W", phi=2.0)
+    blk = np.arange(k) // kblk
+    A *= (2.0 ** (-7 * blk))[None, None, :]      # exact power-of-two scalings
+    B *= (2.0 ** (-3 * blk))[None, :, None]
+    A[:, 5, :kblk] = 0.0
+    got = to_np(mpx.gemm_ozaki_dd(to_gpu(A), to_gpu(B), 5, beta=21, kblk=kblk))
+    rows, cols = np.divmod(np.arange(m * n), n)
+    want = oracle.ozaki_entries(A, B, rows, cols, s=5, beta=21, kblk=kblk).reshape(2, m, n)
+    assert bits_equal(got, want), first_mismatch(got, want)

@@ -191,7 +191,8 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
  * kernel) on the stream, allocates nothing and may be captured in a HIP
  * graph; calls that overlap on one plan race on its counter.
  * mpx_gemm_batched_autotune times each tiling on the caller's buffers (C is
- * overwritten), keeps the fastest in the plan and returns its index (it
+ * overwritten) in two rounds over all tilings (a tiling's time is its faster
+ * round), keeps the fastest in the plan and returns its index (it
  * synchronises the stream).  Errors as for mpx_gemm. */
 typedef struct mpx_gemm_plan_s *mpx_gemm_plan;
 int mpx_gemm_batched_plan(mpx_gemm_plan *out, int prec, int64_t count, const int64_t *m_host,
@@ -218,9 +219,11 @@ int mpx_gemm_variant(int prec, int variant, int transA, int transB, int64_t m, i
                      int64_t ldb, int64_t psB, void *C, int64_t ldc, int64_t psC,
                      void *stream);
 /* Time every variant `reps` times on the given buffers (C is overwritten)
- * with HIP events on `stream`, remember the fastest for this bucket and
- * return its index (>= 0) or a negative status; *best_ms (nullable) receives
- * its mean time.  Synchronises `stream`; must not be called under graph
+ * with HIP events on `stream`, in two rounds over all variants (a variant's
+ * time is its faster round, so an engine clock still ramping up during the
+ * first round does not favour the variants timed last), remember the fastest
+ * for this bucket and return its index (>= 0) or a negative status; *best_ms
+ * (nullable) receives its mean time per call.  Synchronises `stream`; must not be called under graph
  * capture. */
 int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k,
                       const void *A, int64_t lda, int64_t psA, const void *B, int64_t ldb,
@@ -338,7 +341,8 @@ int mpx_polyroots(mpx_plan plan, const void *coef_re, const void *coef_im, int64
 int mpx_plan_destroy(mpx_plan plan);
 /* Launch-shape variants (roots per lane, resident waves per CU); results do
  * not depend on the variant.  The autotuner runs each for iters_probe sweeps
- * on a private copy of the given start roots, keeps the fastest in the plan
+ * on a private copy of the given start roots, in two rounds over all variants
+ * (a variant's time is its faster round), keeps the fastest in the plan
  * and returns its index (or a negative status).  Synchronises; allocates. */
 int mpx_polyroots_variant_count(void);
 int mpx_polyroots_set_variant(mpx_plan plan, int variant);

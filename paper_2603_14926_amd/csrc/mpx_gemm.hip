@@ -353,9 +353,11 @@ extern "C" int mpx_gemm_variant(int prec, int variant, int transA, int transB, i
 }
 
 // Autotuner: time every variant `reps` times on the caller's buffers (C is
-// overwritten) with HIP events on `stream`, remember the fastest for this
-// (precision, transposes, size bucket), and return its index.  Synchronises
-// the stream; not capture-safe.
+// overwritten) with HIP events on `stream`, in two rounds over all variants,
+// each variant's time being its faster round (the engine clock may still be
+// ramping up during the first round, which would favour the variants timed
+// last); remember the fastest for this (precision, transposes, size bucket)
+// and return its index.  Synchronises the stream; not capture-safe.
 extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, int64_t n,
                                  int64_t k, const void* A, int64_t lda, int64_t psA,
                                  const void* B, int64_t ldb, int64_t psB, void* C, int64_t ldc,
@@ -370,15 +372,15 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
     const auto& vs = variants(prec);
     int best = -1;
     float best_t = 0.f;
-    for (int v = 0; v < (int)vs.size(); ++v) {
-        if ((st = vs[v].fn(g, s))) break;  // warm-up
-        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
-        for (int r = 0; r < reps && !st; ++r) st = vs[v].fn(g, s);
-        float ms = 0.f;
-        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
-        ms /= reps;
-        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
-    }
+    for (int round = 0; round < 2 && !st; ++round)
+        for (int v = 0; v < (int)vs.size(); ++v) {
+            if (!ev.start(s)) { st = MPX_EDEVICE; break; }
+            for (int r = 0; r < reps && !st; ++r) st = vs[v].fn(g, s);
+            float ms = 0.f;
+            if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
+            ms /= reps;
+            if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+        }
     if (st) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -439,10 +441,57 @@ k_gemm_batched(int nitems, const GbItem* __restrict__ items, const GbProb* __res
     }
 }
 
+// Wave tiles: each wave of the workgroup pulls its own 8 x 8 item (so the
+// padding of ragged m and n is at most 7 rows / columns) and lane l computes
+// entry (l / 8, l % 8) with the sequential-k multiply-add of the naive loop,
+// operands read straight from global memory (the eight lanes of a row share
+// each A load, the eight of a column each B load).  Loads of U consecutive
+// k are issued before their multiply-adds.  Lanes outside the problem read a
+// clamped (valid) row / column and store nothing.
+template <typename T, int K, int U, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
+                    const GbProb* __restrict__ probs, const T* __restrict__ A, long long psA,
+                    const T* __restrict__ B, long long psB, T* __restrict__ C, long long psC,
+                    int* counter) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane >> 3, lc = lane & 7;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1);
+        it = __shfl(it, 0, 64);
+        if (it >= nitems) break;  // the same value in every lane: uniform exit
+        const GbItem w = items[it];
+        const GbProb q = probs[w.p];
+        const int row = w.m0 + lr, col = w.n0 + lc;
+        const long long ar = (long long)(row < q.m ? row : q.m - 1) * q.k;
+        const long long bc = col < q.n ? col : q.n - 1;
+        const T* __restrict__ Ap = A + q.a;
+        const T* __restrict__ Bp = B + q.b;
+        mpn<T, K> acc = mp_zero<T, K>();
+        int l = 0;
+        for (; l + U <= q.k; l += U) {
+            mpn<T, K> a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a[u] = mp_load<T, K>(Ap, psA, ar + l + u);
+                b[u] = mp_load<T, K>(Bp, psB, (long long)(l + u) * q.n + bc);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = ar_add<AR>(acc, ar_mul<AR>(a[u], b[u]));
+        }
+        for (; l < q.k; ++l)
+            acc = ar_add<AR>(acc, ar_mul<AR>(mp_load<T, K>(Ap, psA, ar + l),
+                                              mp_load<T, K>(Bp, psB, (long long)l * q.n + bc)));
+        if (row < q.m && col < q.n) mp_store<T, K>(C + q.c, psC, (long long)row * q.n + col, acc);
+    }
+}
+
 struct GbVariant {
     int (*launch)(int nitems, const GbItem*, const GbProb*, const void*, long long, const void*,
                   long long, void*, long long, int*, int grid, hipStream_t);
     int bm, bn;
+    int per_wg;  // items a workgroup runs at once (4 for wave tiles)
 };
 
 template <typename T, int K, int TM, int TN, int BK, int AR>
@@ -454,17 +503,29 @@ static int gb_launch(int nitems, const GbItem* items, const GbProb* probs, const
     return launch_status();
 }
 
-// Tilings offered for batches: the regular GEMM's, smallest tiles first
-// (small problems need many tiles to fill the chip).
+template <typename T, int K, int U, int AR>
+static int gb_launch_wave(int nitems, const GbItem* items, const GbProb* probs, const void* A,
+                          long long psA, const void* B, long long psB, void* C, long long psC,
+                          int* counter, int grid, hipStream_t s) {
+    k_gemm_batched_wave<T, K, U, AR><<<grid, kGemmThreads, 0, s>>>(
+        nitems, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
+    return launch_status();
+}
+
+// Tilings offered for batches: 8 x 8 wave tiles, then the regular GEMM's,
+// smallest tiles first (small problems need many tiles to fill the chip, and
+// small tiles waste less on ragged edges).
 static std::vector<GbVariant> gb_variants(int prec) {
-#define MPX_GB(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_>, 16 * TM_, 16 * TN_}
+#define MPX_GB(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_>, 16 * TM_, 16 * TN_, 1}
+#define MPX_GBW(T_, K_, U_, AR_) GbVariant{gb_launch_wave<T_, K_, U_, AR_>, 8, 8, kGemmThreads / 64}
     switch (prec) {
-        case MPX_DD: return {MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF)};
-        case MPX_TD: return {MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
-        case MPX_QD: return {MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
-        case MPX_FF: return {MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF)};
+        case MPX_DD: return {MPX_GBW(double, 2, 4, AR_BF), MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF)};
+        case MPX_TD: return {MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
+        case MPX_QD: return {MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
+        case MPX_FF: return {MPX_GBW(float, 2, 4, AR_BF), MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF)};
         default: return {};
     }
+#undef MPX_GBW
 #undef MPX_GB
 }
 
@@ -589,7 +650,8 @@ static int gb_run(mpx_gemm_plan p, int v, const void* A, int64_t psA, const void
     k_gb_reset<<<1, 1, 0, s>>>(p->counter);
     int st = launch_status();
     if (st) return st;
-    const int grid = std::min(ni, p->cus * 8);
+    const int per = p->vars[v].per_wg;
+    const int grid = (int)std::min<long long>((ni + per - 1) / per, (long long)p->cus * 8);
     return p->vars[v].launch(ni, p->items + p->item_off[v], p->probs, A, psA, B, psB, C, psC,
                              p->counter, grid, s);
 }
@@ -612,15 +674,17 @@ extern "C" int mpx_gemm_batched_autotune(mpx_gemm_plan p, const void* A, int64_t
     if (!ev.ok) return MPX_EDEVICE;
     int best = -1;
     float best_t = 0.f;
-    for (int v = 0; v < (int)p->vars.size() && !st; ++v) {
-        if ((st = gb_run(p, v, A, psA, B, psB, C, psC, s))) break;  // warm-up
-        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
-        for (int r = 0; r < reps && !st; ++r) st = gb_run(p, v, A, psA, B, psB, C, psC, s);
-        float ms = 0.f;
-        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
-        ms /= reps;
-        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
-    }
+    // two rounds over all variants, each variant's faster round counts (as
+    // in mpx_gemm_autotune)
+    for (int round = 0; round < 2 && !st; ++round)
+        for (int v = 0; v < (int)p->vars.size() && !st; ++v) {
+            if (!ev.start(s)) { st = MPX_EDEVICE; break; }
+            for (int r = 0; r < reps && !st; ++r) st = gb_run(p, v, A, psA, B, psB, C, psC, s);
+            float ms = 0.f;
+            if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
+            ms /= reps;
+            if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+        }
     if (st) return st;
     p->variant = best < 0 ? 0 : best;
     if (best_ms) *best_ms = best_t;

@@ -971,21 +971,24 @@ extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const voi
     p->flags &= ~(unsigned)MPX_DK_INIT;
     int best = -1;
     float best_t = 0.f;
-    for (int v = 0; v < kDkVariantCount && !st; ++v) {
-        for (int c = 0; c < p->K && !st; ++c) {
-            if (hipMemcpyAsync(tre + (size_t)c * p->total_roots, (const double*)roots_re + (size_t)c * psr,
-                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(tim + (size_t)c * p->total_roots, (const double*)roots_im + (size_t)c * psr,
-                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                st = MPX_EDEVICE;
+    // two rounds over all variants, each variant's faster round counts (the
+    // engine clock may still be ramping up during the first)
+    for (int round = 0; round < 2 && !st; ++round)
+        for (int v = 0; v < kDkVariantCount && !st; ++v) {
+            for (int c = 0; c < p->K && !st; ++c) {
+                if (hipMemcpyAsync(tre + (size_t)c * p->total_roots, (const double*)roots_re + (size_t)c * psr,
+                                   plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                    hipMemcpyAsync(tim + (size_t)c * p->total_roots, (const double*)roots_im + (size_t)c * psr,
+                                   plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    st = MPX_EDEVICE;
+            }
+            if (st) break;
+            if (!ev.start(s)) { st = MPX_EDEVICE; break; }
+            st = launch_dk(p, v, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);
+            float ms = 0.f;
+            if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
+            if (best < 0 || ms < best_t) { best = v; best_t = ms; }
         }
-        if (st) break;
-        if (!ev.start(s)) { st = MPX_EDEVICE; break; }
-        st = launch_dk(p, v, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);
-        float ms = 0.f;
-        if (st || !ev.stop(s) || !ev.elapsed(&ms)) { st = st ? st : MPX_EDEVICE; break; }
-        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
-    }
     p->iters = saved_iters;
     p->flags = saved_flags;
     if (hipStreamSynchronize(s) != hipSuccess && !st) st = MPX_EDEVICE;  // before freeing tmp

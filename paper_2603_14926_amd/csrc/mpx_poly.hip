@@ -474,18 +474,25 @@ k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
     }
 }
 
-// Persistent iteration kernel: waves pull polynomials in LPT order.
+// Persistent iteration kernel: one-wave workgroups pull polynomials in LPT
+// order.  The slot goes through LDS rather than a lane shuffle, so the
+// compiler keeps the per-polynomial values (degree, offsets) in scalar
+// registers.  The barrier after each sweep orders sweep t's writes before
+// sweep t + 1's reads; every lane runs the same number of barriers (the
+// slot, iters and status are the same in every lane).
 template <int K, int R, int AR>
 __global__ void __launch_bounds__(64)
 k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr, int* status,
                 int iters) {
     using C = cplx<K>;
     const int lane = threadIdx.x;
+    __shared__ int s_slot;
     for (;;) {
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(P.counter, 1);
-        slot = __shfl(slot, 0, 64);
-        if (slot >= batch) break;  // wave-uniform exit
+        if (threadIdx.x == 0) s_slot = atomicAdd(P.counter, 1);
+        __syncthreads();
+        const int slot = s_slot;
+        __syncthreads();  // all have read s_slot before it is overwritten
+        if (slot >= batch) break;  // the same value in every thread: uniform exit
         const int b = P.order[slot];
         const int n = P.degree[b];
         const long long co = P.coef_off[b], ro = P.root_off[b];

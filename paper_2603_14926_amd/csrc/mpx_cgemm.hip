@@ -94,9 +94,9 @@ extern "C" int mpx_cgemm_3m(int prec, int64_t m, int64_t n, int64_t k, const voi
                             int64_t ldc, int64_t psC, void* ws, size_t ws_bytes, void* stream) {
     if (!prec_k(prec)) return MPX_EPREC;
     if (m < 0 || n < 0 || k < 0) return MPX_EINVAL;
-    if (m > 0 && k > 0 && (!Are || !Aim || lda < k || psA < (m - 1) * lda + k)) return MPX_EINVAL;
-    if (k > 0 && n > 0 && (!Bre || !Bim || ldb < n || psB < (k - 1) * ldb + n)) return MPX_EINVAL;
-    if (m > 0 && n > 0 && (!Cre || !Cim || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
+    if (m > 0 && k > 0 && (!Are || !Aim || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
+    if (k > 0 && n > 0 && (!Bre || !Bim || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (!Cre || !Cim || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
     if (m == 0 || n == 0) return MPX_OK;
     const size_t need = cgemm_workspace(prec, m, n, k);
     if (!ws || ws_bytes < need) return MPX_EWORKSPACE;

@@ -310,9 +310,9 @@ static int check_gemm(int prec, int tA, int tB, int64_t m, int64_t n, int64_t k,
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return MPX_ENOTSUP;
     const int64_t ar = tA ? k : m, ac = tA ? m : k;  // stored shape of A
     const int64_t br = tB ? n : k, bc = tB ? k : n;  // stored shape of B
-    if (ar > 0 && ac > 0 && (A == nullptr || lda < ac || psA < (ar - 1) * lda + ac)) return MPX_EINVAL;
-    if (br > 0 && bc > 0 && (B == nullptr || ldb < bc || psB < (br - 1) * ldb + bc)) return MPX_EINVAL;
-    if (m > 0 && n > 0 && (C == nullptr || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
+    if (ar > 0 && ac > 0 && (A == nullptr || !span_fits(ar, ac, lda, psA))) return MPX_EINVAL;
+    if (br > 0 && bc > 0 && (B == nullptr || !span_fits(br, bc, ldb, psB))) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
     return MPX_OK;
 }
 

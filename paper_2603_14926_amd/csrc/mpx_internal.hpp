@@ -50,6 +50,20 @@ inline int launch_status() {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Does a row-major rows x cols block with leading dimension ld fit in a
+// plane of ps elements, i.e. ld >= cols and (rows - 1) ld + cols <= ps?
+// Evaluated without signed overflow (a span beyond int64 does not fit).
+// rows, cols >= 1.
+inline bool span_fits(int64_t rows, int64_t cols, int64_t ld, int64_t ps) {
+    if (ld < cols) return false;
+    if (rows > 1 && ld > (INT64_MAX - cols) / (rows - 1)) return false;
+    return (rows - 1) * ld + cols <= ps;
+}
+// a * b <= ps for a, b >= 0, without signed overflow.
+inline bool prod_fits(int64_t a, int64_t b, int64_t ps) {
+    return b == 0 || a <= ps / b;
+}
+
 // Two HIP events bracketing timed work on a stream (the autotuners); both are
 // destroyed on scope exit.  Every step reports failure instead of ignoring it.
 struct EventPair {

@@ -396,9 +396,9 @@ extern "C" int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double* 
     // 2^(2 beta) (1 + max(0, s-2)/4) per k; over kblk terms this must stay
     // <= 2^53 (every partial sum is then an exactly representable integer).
     if (!oz_exact(slices, beta, kblk)) return MPX_EINVAL;
-    if (m > 0 && k > 0 && (A == nullptr || lda < k || psA < (m - 1) * lda + k)) return MPX_EINVAL;
-    if (k > 0 && n > 0 && (B == nullptr || ldb < n || psB < (k - 1) * ldb + n)) return MPX_EINVAL;
-    if (m > 0 && n > 0 && (C == nullptr || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
+    if (m > 0 && k > 0 && (A == nullptr || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
+    if (k > 0 && n > 0 && (B == nullptr || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
     if (m == 0 || n == 0) return MPX_OK;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2) return MPX_ENOTSUP;
     const size_t need = ozaki_workspace(m, n, k, slices);

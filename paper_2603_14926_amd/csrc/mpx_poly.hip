@@ -661,10 +661,11 @@ using namespace mpx;
 static int polyval_check(int prec, int64_t batch, int64_t deg, const void* coef, int64_t psc,
                          const void* x, int64_t psx) {
     if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
-    if (batch < 0 || deg < 0) return MPX_EINVAL;
+    if (batch < 0 || deg < 0 || deg == INT64_MAX) return MPX_EINVAL;
     if (batch > INT32_MAX) return MPX_ENOTSUP;  // grid dimensions
     if (batch == 0) return MPX_OK;
-    if (coef == nullptr || psc < batch * (deg + 1) || x == nullptr || psx < batch) return MPX_EINVAL;
+    if (coef == nullptr || !prod_fits(batch, deg + 1, psc) || x == nullptr || psx < batch)
+        return MPX_EINVAL;
     return MPX_OK;
 }
 
@@ -699,7 +700,7 @@ template <int K>
 static int estrin_t(long long batch, long long deg, const void* coef, long long psc, const void* x,
                     long long psx, void* y, long long psy, hipStream_t s) {
     int L = 0;
-    while ((1LL << L) < deg + 1) ++L;
+    while (L < 62 && (1LL << L) < deg + 1) ++L;  // beyond the supported depths: ENOTSUP below
     const int LB = L > 6 ? L - 6 : 0;
     const unsigned blocks = (unsigned)ceil_div(batch, 4);
 #define MPX_ES(LBV)                                                                             \
@@ -720,7 +721,7 @@ static int estrin_cplx_t(long long batch, long long deg, const void* coef, long 
                          const void* xre, const void* xim, long long psx, void* yre, void* yim,
                          long long psy, hipStream_t s) {
     int L = 0;
-    while ((1LL << L) < deg + 1) ++L;
+    while (L < 62 && (1LL << L) < deg + 1) ++L;  // beyond the supported depths: ENOTSUP below
     const int LB = L > 6 ? L - 6 : 0;
     const unsigned blocks = (unsigned)ceil_div(batch, 4);
 #define MPX_EC(LBV)                                                                            \
@@ -803,7 +804,7 @@ extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const 
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (gy == nullptr || psg < batch) return MPX_EINVAL;
-    if (gcoef && psgc < batch * (deg + 1)) return MPX_EINVAL;
+    if (gcoef && !prod_fits(batch, deg + 1, psgc)) return MPX_EINVAL;
     if (gx && psgx < batch) return MPX_EINVAL;
     if (!gcoef && !gx) return MPX_OK;
     const unsigned blocks = (unsigned)ceil_div(batch, 64);

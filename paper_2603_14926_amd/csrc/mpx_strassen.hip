@@ -222,9 +222,9 @@ extern "C" int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, cons
     if (!K || base_prec(prec) == MPX_FF) return MPX_EPREC;
     if (m < 0 || n < 0 || k < 0 || cutoff < 2) return MPX_EINVAL;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2) return MPX_ENOTSUP;
-    if (m > 0 && k > 0 && (A == nullptr || lda < k || psA < (m - 1) * lda + k)) return MPX_EINVAL;
-    if (k > 0 && n > 0 && (B == nullptr || ldb < n || psB < (k - 1) * ldb + n)) return MPX_EINVAL;
-    if (m > 0 && n > 0 && (C == nullptr || ldc < n || psC < (m - 1) * ldc + n)) return MPX_EINVAL;
+    if (m > 0 && k > 0 && (A == nullptr || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
+    if (k > 0 && n > 0 && (B == nullptr || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
     if (st_levels(m, k, n, cutoff, nullptr, K) > kStMaxLevels) return MPX_ENOTSUP;
     if (m == 0 || n == 0) return MPX_OK;
     const size_t need = strassen_workspace(prec, m, n, k, cutoff);

@@ -398,7 +398,7 @@ extern "C" int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void* A
     if (m < 0 || n < 0 || (trans != 0 && trans != 1)) return MPX_EINVAL;
     if (m > INT32_MAX || n > INT32_MAX) return MPX_ENOTSUP;  // grid dimensions
     const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
-    if (m > 0 && n > 0 && (A == nullptr || lda < n || psA < (m - 1) * lda + n)) return MPX_EINVAL;
+    if (m > 0 && n > 0 && (A == nullptr || !span_fits(m, n, lda, psA))) return MPX_EINVAL;
     int st;
     if ((st = check_vec(prec, xlen, x, psx)) || (st = check_vec(prec, ylen, y, psy))) return st;
     if (ylen == 0) return MPX_OK;

@@ -124,3 +124,25 @@ def test_probe_rejects_bad_arguments():
     assert L.mpx_probe_valu(0, 0, FAKE, 256, None) == -1       # iters < 1
     assert L.mpx_probe_valu(0, 1, FAKE, 300, None) == -1       # not a multiple of 256
     assert L.mpx_probe_valu(0, 1, None, 256, None) == -1       # null output
+
+
+def test_strides_whose_span_overflows_int64_rejected():
+    """A leading dimension or degree so large that the needed span does not
+    fit in int64 is an argument error (the check must not wrap around)."""
+    L = mpx.lib()
+    big = 1 << 62
+    # (m - 1) * lda + k would be 2 * 2^62 + 4: beyond int64
+    assert L.mpx_gemm(4, 0, 0, 3, 4, 4, FAKE, big, 16, FAKE, 4, 16, FAKE, 4, 16, None) == -1
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 3, FAKE, 4, 16, FAKE, big, 16, FAKE, 4, 16, None) == -1
+    assert L.mpx_gemm(4, 0, 0, 3, 4, 4, FAKE, 4, 16, FAKE, 4, 16, FAKE, big, 16, None) == -1
+    assert L.mpx_gemv(4, 0, 3, 4, FAKE, big, 16, FAKE, 4, FAKE, 4, None, 0, None) == -1
+    assert L.mpx_gemm_strassen(4, 3, 4, 4, FAKE, big, 16, FAKE, 4, 16, FAKE, 4, 16, 2, FAKE, 1 << 20,
+                               None) == -1
+    assert L.mpx_cgemm_3m(4, 3, 4, 4, FAKE, FAKE, big, 16, FAKE, FAKE, 4, 16, FAKE, FAKE, 4, 16, FAKE,
+                          1 << 20, None) == -1
+    assert L.mpx_gemm_ozaki_dd(3, 4, 4, FAKE, big, 16, FAKE, 4, 16, FAKE, 4, 16, 4, 20, 64, FAKE,
+                               1 << 20, None) == -1
+    # batch * (deg + 1) would be 4 * 2^62: beyond int64
+    assert L.mpx_polyval(4, 4, big, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1
+    assert L.mpx_polyval_estrin(4, 4, big, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1
+    assert L.mpx_polyval(4, 4, (1 << 63) - 1, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1

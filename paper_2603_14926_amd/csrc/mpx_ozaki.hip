@@ -31,6 +31,7 @@
 #include "mpx_internal.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 namespace mpx {
@@ -312,7 +313,7 @@ k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, lon
 constexpr int oz_ta(int S) { return S <= 6 ? 2 : 1; }
 
 // Stage depth of the slice GEMM: 0 = 8 k per LDS stage, 1 = 16 k per stage.
-static int g_oz_variant = 0;
+static std::atomic<int> g_oz_variant{0};  // read by every call, set by mpx_gemm_ozaki_set_variant
 
 static bool oz_exact(int slices, int beta, long long kblk) {
     if (beta > 26) return false;
@@ -372,7 +373,7 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     if ((st = launch_status())) return st;
     constexpr int TA = oz_ta(S);
     const int tn = (int)(d.np / 32), tm = (int)(d.mp / (32 * TA));
-    if (g_oz_variant == 1)
+    if (g_oz_variant.load(std::memory_order_relaxed) == 1)
         k_oz_gemm<S, TA, 1, 16><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
             m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
     else
@@ -420,6 +421,6 @@ extern "C" int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double* 
 // k per LDS stage).  Results do not depend on it.
 extern "C" int mpx_gemm_ozaki_set_variant(int variant) {
     if (variant < 0 || variant > 1) return MPX_EINVAL;
-    g_oz_variant = variant;
+    g_oz_variant.store(variant, std::memory_order_relaxed);
     return MPX_OK;
 }

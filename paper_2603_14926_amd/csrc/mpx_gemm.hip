@@ -245,6 +245,7 @@ static const std::vector<Variant>& variants(int prec) {
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td")};
     static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
     static const std::vector<Variant> ff = {
+        {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},
         {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},
         {run_variant<float, 2, 2, 4, 8, AR_BF>, 32, 64, "ff_2x4_k8"},
         {run_variant<float, 2, 2, 2, 16, AR_BF>, 32, 32, "ff_2x2_k16"},

@@ -34,7 +34,10 @@
  * (plans keep the buffers they are given, see below).  Inputs are assumed
  * finite and normal (Section 2); NaN / Inf / subnormal handling is
  * unspecified.  Outputs may alias inputs only for mpx_add / mpx_mul (z may
- * equal x or y) and mpx_axpy (y in place).
+ * equal x or y) and mpx_axpy (y in place).  The dot, GEMV and GEMM family
+ * (plain, batched, Strassen, 3M, Ozaki) reject with MPX_EINVAL an output
+ * whose memory range (all K planes) overlaps an input's, or a workspace
+ * overlapping any operand.
  *
  * Determinism: every call is bitwise reproducible for the same arguments.
  * Elementwise ops, AXPY, GEMM (plain, batched, Strassen, 3M), Horner,

@@ -97,9 +97,25 @@ extern "C" int mpx_cgemm_3m(int prec, int64_t m, int64_t n, int64_t k, const voi
     if (m > 0 && k > 0 && (!Are || !Aim || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
     if (k > 0 && n > 0 && (!Bre || !Bim || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
     if (m > 0 && n > 0 && (!Cre || !Cim || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
+    // the outputs must not overlap the inputs or each other, nor the
+    // workspace any operand
+    const int K = prec_k(prec);
+    const size_t elt = is_ff(prec) ? sizeof(float) : sizeof(double);
+    const uint64_t cb = planes_bytes(K, m, n, ldc, psC, elt);
+    const uint64_t ab = planes_bytes(K, m, k, lda, psA, elt), bb = planes_bytes(K, k, n, ldb, psB, elt);
+    for (const void* c : {(const void*)Cre, (const void*)Cim})
+        if (overlaps(c, cb, Are, ab) || overlaps(c, cb, Aim, ab) || overlaps(c, cb, Bre, bb) ||
+            overlaps(c, cb, Bim, bb))
+            return MPX_EINVAL;
+    if (overlaps(Cre, cb, Cim, cb)) return MPX_EINVAL;
     if (m == 0 || n == 0) return MPX_OK;
     const size_t need = cgemm_workspace(prec, m, n, k);
     if (!ws || ws_bytes < need) return MPX_EWORKSPACE;
+    for (const void* q : {(const void*)Are, (const void*)Aim})
+        if (overlaps(ws, need, q, ab)) return MPX_EINVAL;
+    for (const void* q : {(const void*)Bre, (const void*)Bim})
+        if (overlaps(ws, need, q, bb)) return MPX_EINVAL;
+    if (overlaps(ws, need, Cre, cb) || overlaps(ws, need, Cim, cb)) return MPX_EINVAL;
     hipStream_t s = as_stream(stream);
     switch (prec) {
         case MPX_DD: return cgemm_t<double, 2>(prec, m, n, k, Are, Aim, lda, psA, Bre, Bim, ldb, psB, Cre, Cim, ldc, psC, ws, s);

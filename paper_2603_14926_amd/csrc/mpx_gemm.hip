@@ -314,6 +314,13 @@ static int check_gemm(int prec, int tA, int tB, int64_t m, int64_t n, int64_t k,
     if (ar > 0 && ac > 0 && (A == nullptr || !span_fits(ar, ac, lda, psA))) return MPX_EINVAL;
     if (br > 0 && bc > 0 && (B == nullptr || !span_fits(br, bc, ldb, psB))) return MPX_EINVAL;
     if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
+    // C must not overlap A or B (the kernels read them while C is written)
+    const int K = prec_k_ar(prec);
+    const size_t elt = is_ff(prec) ? sizeof(float) : sizeof(double);
+    const uint64_t bc_ = planes_bytes(K, m, n, ldc, psC, elt);
+    if (overlaps(C, bc_, A, planes_bytes(K, ar, ac, lda, psA, elt)) ||
+        overlaps(C, bc_, B, planes_bytes(K, br, bc, ldb, psB, elt)))
+        return MPX_EINVAL;
     return MPX_OK;
 }
 
@@ -640,6 +647,12 @@ static int gb_check(mpx_gemm_plan p, const void* A, int64_t psA, const void* B, 
     if (p->totA > 0 && (!A || psA < p->totA)) return MPX_EINVAL;
     if (p->totB > 0 && (!B || psB < p->totB)) return MPX_EINVAL;
     if (p->totC > 0 && (!C || psC < p->totC)) return MPX_EINVAL;
+    const int K = mpx::prec_k(p->prec);
+    const size_t elt = mpx::is_ff(p->prec) ? sizeof(float) : sizeof(double);
+    const uint64_t bc = mpx::planes_bytes(K, 1, p->totC, p->totC, psC, elt);
+    if (mpx::overlaps(C, bc, A, mpx::planes_bytes(K, 1, p->totA, p->totA, psA, elt)) ||
+        mpx::overlaps(C, bc, B, mpx::planes_bytes(K, 1, p->totB, p->totB, psB, elt)))
+        return MPX_EINVAL;  // C must not overlap A or B
     return MPX_OK;
 }
 

@@ -64,6 +64,23 @@ inline bool prod_fits(int64_t a, int64_t b, int64_t ps) {
     return b == 0 || a <= ps / b;
 }
 
+// Bytes spanned by K component planes of a rows x cols row-major block
+// (plane stride ps, leading dimension ld, elements of elt bytes), computed
+// in 128 bits and saturated; 0 for an empty block.
+inline uint64_t planes_bytes(int K, int64_t rows, int64_t cols, int64_t ld, int64_t ps, size_t elt) {
+    if (rows <= 0 || cols <= 0) return 0;
+    const unsigned __int128 e = (unsigned __int128)(K - 1) * (uint64_t)ps +
+                                (unsigned __int128)(rows - 1) * (uint64_t)ld + (uint64_t)cols;
+    const unsigned __int128 b = e * elt;
+    return b > (unsigned __int128)UINT64_MAX ? UINT64_MAX : (uint64_t)b;
+}
+// Do the byte ranges [a, a + na) and [b, b + nb) intersect?
+inline bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
+    if (na == 0 || nb == 0 || a == nullptr || b == nullptr) return false;
+    const unsigned __int128 a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
 // Two HIP events bracketing timed work on a stream (the autotuners); both are
 // destroyed on scope exit.  Every step reports failure instead of ignoring it.
 struct EventPair {

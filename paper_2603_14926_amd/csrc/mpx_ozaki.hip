@@ -400,10 +400,17 @@ extern "C" int mpx_gemm_ozaki_dd(int64_t m, int64_t n, int64_t k, const double* 
     if (m > 0 && k > 0 && (A == nullptr || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
     if (k > 0 && n > 0 && (B == nullptr || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
     if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
+    // C must not overlap A or B, nor the workspace any of them
+    const uint64_t cb = planes_bytes(2, m, n, ldc, psC, sizeof(double));
+    const uint64_t ab = planes_bytes(2, m, k, lda, psA, sizeof(double));
+    const uint64_t bb = planes_bytes(2, k, n, ldb, psB, sizeof(double));
+    if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb)) return MPX_EINVAL;
     if (m == 0 || n == 0) return MPX_OK;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2) return MPX_ENOTSUP;
     const size_t need = ozaki_workspace(m, n, k, slices);
     if (ws == nullptr || ws_bytes < need) return MPX_EWORKSPACE;
+    if (overlaps(ws, need, A, ab) || overlaps(ws, need, B, bb) || overlaps(ws, need, C, cb))
+        return MPX_EINVAL;
     hipStream_t s = as_stream(stream);
 #define MPX_OZ(SS)                                                                     \
     case SS:                                                                           \

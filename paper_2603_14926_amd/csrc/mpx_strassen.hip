@@ -225,10 +225,17 @@ extern "C" int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, cons
     if (m > 0 && k > 0 && (A == nullptr || !span_fits(m, k, lda, psA))) return MPX_EINVAL;
     if (k > 0 && n > 0 && (B == nullptr || !span_fits(k, n, ldb, psB))) return MPX_EINVAL;
     if (m > 0 && n > 0 && (C == nullptr || !span_fits(m, n, ldc, psC))) return MPX_EINVAL;
+    // C must not overlap A or B, nor the workspace any of them
+    const uint64_t cb = planes_bytes(K, m, n, ldc, psC, sizeof(double));
+    const uint64_t ab = planes_bytes(K, m, k, lda, psA, sizeof(double));
+    const uint64_t bb = planes_bytes(K, k, n, ldb, psB, sizeof(double));
+    if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb)) return MPX_EINVAL;
     if (st_levels(m, k, n, cutoff, nullptr, K) > kStMaxLevels) return MPX_ENOTSUP;
     if (m == 0 || n == 0) return MPX_OK;
     const size_t need = strassen_workspace(prec, m, n, k, cutoff);
     if (need > 0 && (ws == nullptr || ws_bytes < need)) return MPX_EWORKSPACE;
+    if (overlaps(ws, need, A, ab) || overlaps(ws, need, B, bb) || overlaps(ws, need, C, cb))
+        return MPX_EINVAL;
     hipStream_t s = as_stream(stream);
     switch (prec) {
         case MPX_DD: return strassen_t<double, 2, AR_BF>(prec, m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC, cutoff, ws, s);

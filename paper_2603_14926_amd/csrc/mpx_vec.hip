@@ -391,6 +391,14 @@ extern "C" int mpx_dot(int prec, int64_t n, const void* x, int64_t psx, const vo
     if (result == nullptr) return MPX_EINVAL;
     const size_t need = dot_workspace(prec, n);
     if (need > 0 && (ws == nullptr || ws_bytes < need)) return MPX_EWORKSPACE;
+    // neither the result nor the workspace may overlap an input or each other
+    const int K = prec_k_ar(prec);
+    const size_t elt = is_ff(base_prec(prec)) ? sizeof(float) : sizeof(double);
+    const uint64_t xb = planes_bytes(K, 1, n, n, psx, elt), yb = planes_bytes(K, 1, n, n, psy, elt);
+    const uint64_t rb = (uint64_t)K * elt;
+    if (overlaps(result, rb, x, xb) || overlaps(result, rb, y, yb) || overlaps(ws, need, x, xb) ||
+        overlaps(ws, need, y, yb) || overlaps(ws, need, result, rb))
+        return MPX_EINVAL;
     MPX_DISPATCH_AR(prec, launch_dot, n, x, psx, y, psy, result, ws, as_stream(stream));
 }
 
@@ -404,9 +412,17 @@ extern "C" int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void* A
     if (m > 0 && n > 0 && (A == nullptr || !span_fits(m, n, lda, psA))) return MPX_EINVAL;
     int st;
     if ((st = check_vec(prec, xlen, x, psx)) || (st = check_vec(prec, ylen, y, psy))) return st;
+    // y must not overlap A or x, nor the workspace any of them
+    const int K = prec_k(prec);
+    const size_t elt = is_ff(prec) ? sizeof(float) : sizeof(double);
+    const uint64_t ab = planes_bytes(K, m, n, lda, psA, elt);
+    const uint64_t xb = planes_bytes(K, 1, xlen, xlen, psx, elt), yb = planes_bytes(K, 1, ylen, ylen, psy, elt);
+    if (overlaps(y, yb, A, ab) || overlaps(y, yb, x, xb)) return MPX_EINVAL;
     if (ylen == 0) return MPX_OK;
     const size_t need = gemv_workspace(prec, m, n, trans);
     if (need > 0 && (ws == nullptr || ws_bytes < need)) return MPX_EWORKSPACE;
+    if (overlaps(ws, need, A, ab) || overlaps(ws, need, x, xb) || overlaps(ws, need, y, yb))
+        return MPX_EINVAL;
     MPX_DISPATCH(prec, launch_gemv, trans, m, n, A, lda, psA, x, psx, y, psy, ws,
                  as_stream(stream));
 }

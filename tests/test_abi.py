@@ -146,3 +146,26 @@ def test_strides_whose_span_overflows_int64_rejected():
     assert L.mpx_polyval(4, 4, big, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1
     assert L.mpx_polyval_estrin(4, 4, big, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1
     assert L.mpx_polyval(4, 4, (1 << 63) - 1, FAKE, 10, FAKE, 4, FAKE, 4, None) == -1
+
+
+def test_overlapping_outputs_rejected():
+    """Outputs that overlap an input, and workspaces that overlap an operand,
+    are argument errors for the dot / GEMV / GEMM family (checked before any
+    launch, on the pointer ranges of all K planes)."""
+    L = mpx.lib()
+    base = 1 << 40                        # fake device addresses, never dereferenced
+    A, B, Cp = C.c_void_p(base), C.c_void_p(base + (1 << 20)), C.c_void_p(base + (2 << 20))
+    inside_A = C.c_void_p(base + 3 * 16 * 8)   # within plane 3 of a QD 4 x 4 matrix at A
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 4, A, 4, 16, B, 4, 16, A, 4, 16, None) == -1         # C == A
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 4, A, 4, 16, B, 4, 16, inside_A, 4, 16, None) == -1  # C in A
+    assert L.mpx_gemm(4, 0, 0, 4, 4, 4, A, 4, 16, B, 4, 16, B, 4, 16, None) == -1         # C == B
+    assert L.mpx_gemm_strassen(4, 4, 4, 4, A, 4, 16, B, 4, 16, A, 4, 16, 2, Cp, 1 << 20, None) == -1
+    assert L.mpx_gemm_ozaki_dd(4, 4, 4, A, 4, 16, B, 4, 16, B, 4, 16, 4, 20, 64, Cp, 1 << 20,
+                               None) == -1
+    assert L.mpx_gemm_ozaki_dd(4, 4, 4, A, 4, 16, B, 4, 16, Cp, 4, 16, 4, 20, 64, A, 1 << 20,
+                               None) == -1                                                  # ws == A
+    assert L.mpx_cgemm_3m(4, 4, 4, 4, A, B, 4, 16, Cp, C.c_void_p(base + (3 << 20)), 4, 16,
+                          A, C.c_void_p(base + (5 << 20)), 4, 16, C.c_void_p(base + (6 << 20)),
+                          1 << 20, None) == -1                                              # Cre == Are
+    assert L.mpx_gemv(4, 0, 4, 4, A, 4, 16, B, 4, inside_A, 4, None, 0, None) == -1         # y in A
+    assert L.mpx_dot(4, 8, A, 8, B, 8, C.c_void_p(base + 8 * 8), None, 0, None) == -1      # result in x

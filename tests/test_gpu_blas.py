@@ -13,6 +13,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
+from tests import paper_values
 from oracle import exact
 from paper_2603_14926_amd import mpx, synth
 from tests.gpu_util import PREC_K, bits_equal, first_mismatch, to_gpu, to_np
@@ -204,7 +205,9 @@ def test_gemm_paper_matrices_digits():
     import math
     n = 512
     s15 = synth.sqrt_fraction(15, bits=400)
-    for p, K, need in (("dd", 2, 29.0), ("td", 3, 45.5), ("qd", 4, 61.7)):
+    need_by_k = paper_values.gemm_digits("real")     # tests/golden/gemm_digits.txt
+    for p, K in (("dd", 2), ("td", 3), ("qd", 4)):
+        need = need_by_k[K]
         A, B = synth.paper_real_gemm(K, n)
         got = to_np(mpx.gemm(p, to_gpu(A), to_gpu(B)))
         for (i, j) in ((0, 0), (100, 7), (511, 511), (255, 400)):

@@ -9,6 +9,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
+from tests import paper_values
 from oracle import exact
 from paper_2603_14926_amd import mpx, synth
 from tests.gpu_util import bits_equal, first_mismatch, to_gpu, to_np
@@ -33,7 +34,7 @@ def test_cgemm_3m_bit_exact(p, K, mnk):
     assert bits_equal(to_np(gi), wi), first_mismatch(to_np(gi), wi)
 
 
-PAPER_COMPLEX_DIGITS = {2: 23.2, 3: 39.2, 4: 55.8}
+PAPER_COMPLEX_DIGITS = paper_values.gemm_digits("complex")   # tests/golden/gemm_digits.txt
 
 
 @pytest.mark.parametrize("p,K", [("dd", 2), ("td", 3), ("qd", 4)])

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import paper_values
 from oracle import exact
 from paper_2603_14926_amd import synth
 
@@ -128,7 +129,7 @@ def test_gemm_identity_reproduces_value(K):
 
 # Section 3.1: accuracy of the real test matrices a_ij = sqrt5 (i+j-1),
 # b_ij = sqrt3 (n-i+1) is 29.0 / 45.5 / 61.7 significant digits or better.
-PAPER_DIGITS = {2: 29.0, 3: 45.5, 4: 61.7}
+PAPER_DIGITS = paper_values.gemm_digits("real")      # tests/golden/gemm_digits.txt
 
 
 @pytest.mark.parametrize("K", [2, 3, 4])
@@ -175,7 +176,7 @@ def test_ff_layer_against_exact():
 # Section 3.2: complex matrices a = exp(r_n)(r_u - 1/2) + i exp(r_n')(r_u' - 1/2)
 # multiplied by the 3M method reach at least 23.2 / 39.2 / 55.8 significant
 # digits (DD / TD / QD, minimum over real and imaginary parts, n = 2049).
-PAPER_COMPLEX_DIGITS = {2: 23.2, 3: 39.2, 4: 55.8}
+PAPER_COMPLEX_DIGITS = paper_values.gemm_digits("complex")
 
 
 def _complex_inputs(K, n, seed):

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import paper_values
 from oracle import exact
 from paper_2603_14926_amd import synth
 
@@ -63,15 +64,9 @@ def test_two_prod_exact_and_unique():
         assert Fraction(e) == Fraction(a) * Fraction(b) - Fraction(p)
 
 
-# Table 1 and Table 2 (BF rows) and the operation lists of DWBFAdd / DWBFMul.
-COUNTS = {
-    (2, "add"): (8, 12, 0, 0),
-    (2, "mul"): (3, 2, 3, 1),
-    (3, "add"): (21, 36, 0, 0),
-    (3, "mul"): (14, 16, 6, 3),
-    (4, "add"): (37, 66, 0, 0),
-    (4, "mul"): (38, 52, 10, 6),
-}
+# Table 1 and Table 2 (BF rows) and the operation lists of DWBFAdd / DWBFMul
+# (tests/golden/bf_operation_counts.txt).
+COUNTS = paper_values.bf_operation_counts()
 
 
 @pytest.mark.parametrize("key", sorted(COUNTS))

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import paper_values
 from oracle import exact, strassen
 from paper_2603_14926_amd import synth
 
@@ -62,7 +63,7 @@ def test_normwise_error_within_higham_bound(K):
     assert worst <= 2.0 ** -(53 * K - 20) * n * na * nb
 
 
-PAPER_DIGITS = {2: 29.0, 3: 45.5, 4: 61.7}
+PAPER_DIGITS = paper_values.gemm_digits("real")   # tests/golden/gemm_digits.txt
 
 
 @pytest.mark.parametrize("K", [2, 3, 4])

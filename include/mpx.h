@@ -342,8 +342,10 @@ int mpx_polyroots_plan(mpx_plan *out, int prec, int64_t batch, const int32_t *de
 int mpx_polyroots(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
                   void *roots_re, void *roots_im, int64_t psr, int32_t *status, void *stream);
 int mpx_plan_destroy(mpx_plan plan);
-/* Launch-shape variants (roots per lane, resident waves per CU); results do
- * not depend on the variant.  The autotuner runs each for iters_probe sweeps
+/* Launch-shape variants (roots per lane, resident waves per CU, or the packed
+ * schedule: 4-wave jobs built by the plan, each holding whole polynomials
+ * whose 64-root chunks are spread over the waves to balance their loads);
+ * results do not depend on the variant.  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants
  * (a variant's time is its faster round), keeps the fastest in the plan
  * and returns its index (or a negative status).  Synchronises; allocates. */

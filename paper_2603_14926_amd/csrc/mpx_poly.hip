@@ -425,6 +425,11 @@ struct DkPlanDev {
     double* zim;
     int* counter;              // work counter
     long long psm, psz;        // plane strides of the plan buffers
+    // packed schedule (4-wave jobs): job j owns items job_off[j] .. job_off[j+1]-1,
+    // item i = (polynomial, 64-root chunk, wave) at items[3 i .. 3 i + 2]
+    const int* job_off;
+    const int* items;
+    int njobs;
 };
 
 __global__ void k_reset_counter(int* c) { *c = 0; }
@@ -474,6 +479,68 @@ k_dk_prologue(int batch, DkPlanDev P, const double* __restrict__ are,
     }
 }
 
+// One DK update of the roots base, base + 64, ..., base + 64 (R - 1) (those
+// below n) of one polynomial: Horner for q(z_i) on the monic coefficients
+// (mre, mim), the product over j != i of (z_i - z_j) in ascending j, both
+// with power-of-two rescaling, then z_i - q(z_i) / prod, read from the
+// source iterate (sre, sim) and written to the destination (dre, dim).
+template <int K, int R, int AR>
+__device__ __forceinline__ void dk_roots(const DkPlanDev& P, const double* mre, const double* mim,
+                                         const double* sre, const double* sim, long long pss,
+                                         double* dre, double* dim, long long psd, int n,
+                                         long long ro, int base) {
+    using C = cplx<K>;
+    int idx[R];
+    C z[R], h[R];
+    long long E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        idx[r] = base + 64 * r;
+        const int ic = idx[r] < n ? idx[r] : n - 1;
+        z[r] = c_load<K>(sre, sim, pss, ro + ic);
+        h[r].re = mp_from<double, K>(1.0);
+        h[r].im = mp_zero<double, K>();
+        E[r] = 0;
+    }
+    // q(z) by Horner on the monic coefficients
+#pragma nounroll
+    for (int k = n - 1; k >= 0; --k) {
+        const C ck = c_load<K>(mre, mim, P.psm, k);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            h[r] = c_add<K, AR>(c_mul<K, AR>(h[r], z[r]), c_ldexp<K>(ck, clamp_exp(-E[r])));
+            c_rescale<K, true>(h[r], E[r]);
+        }
+    }
+    // prod_{j != i} (z_i - z_j), j ascending
+    C Pp[R];
+    long long F[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        Pp[r].re = mp_from<double, K>(1.0);
+        Pp[r].im = mp_zero<double, K>();
+        F[r] = 0;
+    }
+#pragma nounroll
+    for (int j = 0; j < n; ++j) {
+        const C zj = c_load<K>(sre, sim, pss, ro + j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            C t = c_mul<K, AR>(Pp[r], c_sub<K, AR>(z[r], zj));
+            long long Ft = F[r];
+            c_rescale<K, false>(t, Ft);
+            const bool take = j != idx[r];
+            Pp[r] = c_select<K>(take, t, Pp[r]);
+            F[r] = take ? Ft : F[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const C w = c_ldexp<K>(c_div<K, AR>(h[r], Pp[r]), clamp_exp(E[r] - F[r]));
+        if (idx[r] < n) c_store<K>(dre, dim, psd, ro + idx[r], c_sub<K, AR>(z[r], w));
+    }
+}
+
 // Persistent iteration kernel: one-wave workgroups pull polynomials in LPT
 // order.  The slot goes through LDS rather than a lane shuffle, so the
 // compiler keeps the per-polynomial values (degree, offsets) in scalar
@@ -484,7 +551,6 @@ template <int K, int R, int AR>
 __global__ void __launch_bounds__(64)
 k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr, int* status,
                 int iters) {
-    using C = cplx<K>;
     const int lane = threadIdx.x;
     __shared__ int s_slot;
     for (;;) {
@@ -507,57 +573,8 @@ k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr,
             double* dim = from_user ? P.zim : rim;
             const long long pss = from_user ? psr : P.psz;
             const long long psd = from_user ? P.psz : psr;
-            for (int base = lane; base < n; base += 64 * R) {
-                int idx[R];
-                C z[R], h[R];
-                long long E[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    idx[r] = base + 64 * r;
-                    const int ic = idx[r] < n ? idx[r] : n - 1;
-                    z[r] = c_load<K>(sre, sim, pss, ro + ic);
-                    h[r].re = mp_from<double, K>(1.0);
-                    h[r].im = mp_zero<double, K>();
-                    E[r] = 0;
-                }
-                // q(z) by Horner on the monic coefficients
-#pragma nounroll
-                for (int k = n - 1; k >= 0; --k) {
-                    const C ck = c_load<K>(mre, mim, P.psm, k);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        h[r] = c_add<K, AR>(c_mul<K, AR>(h[r], z[r]), c_ldexp<K>(ck, clamp_exp(-E[r])));
-                        c_rescale<K, true>(h[r], E[r]);
-                    }
-                }
-                // prod_{j != i} (z_i - z_j), j ascending
-                C Pp[R];
-                long long F[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    Pp[r].re = mp_from<double, K>(1.0);
-                    Pp[r].im = mp_zero<double, K>();
-                    F[r] = 0;
-                }
-#pragma nounroll
-                for (int j = 0; j < n; ++j) {
-                    const C zj = c_load<K>(sre, sim, pss, ro + j);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        C t = c_mul<K, AR>(Pp[r], c_sub<K, AR>(z[r], zj));
-                        long long Ft = F[r];
-                        c_rescale<K, false>(t, Ft);
-                        const bool take = j != idx[r];
-                        Pp[r] = c_select<K>(take, t, Pp[r]);
-                        F[r] = take ? Ft : F[r];
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const C w = c_ldexp<K>(c_div<K, AR>(h[r], Pp[r]), clamp_exp(E[r] - F[r]));
-                    if (idx[r] < n) c_store<K>(dre, dim, psd, ro + idx[r], c_sub<K, AR>(z[r], w));
-                }
-            }
+            for (int base = lane; base < n; base += 64 * R)
+                dk_roots<K, R, AR>(P, mre, mim, sre, sim, pss, dre, dim, psd, n, ro, base);
             __syncthreads();  // iterate t complete before t+1 reads it
         }
         if (iters & 1) {  // result is in the plan buffer: copy back to the caller's
@@ -580,13 +597,84 @@ k_durand_kerner(int batch, DkPlanDev P, double* rre, double* rim, long long psr,
     }
 }
 
+// Packed persistent kernel: 4-wave workgroups pull jobs (heaviest first); a
+// job holds whole polynomials whose 64-root chunks the plan spread over the
+// four waves so that their per-sweep loads are nearly equal (a polynomial
+// larger than a wave's share is split across waves, small ones are packed
+// together).  The barrier after each sweep orders sweep t's writes before
+// sweep t + 1's reads for every polynomial of the job; every thread runs the
+// same number of barriers (the job index, iters and status are uniform).
+constexpr int kDkPackedWaves = 4;
+
+template <int K, int AR>
+__global__ void __launch_bounds__(64 * kDkPackedWaves)
+k_dk_packed(DkPlanDev P, double* rre, double* rim, long long psr, int* status, int iters) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __shared__ int s_slot;
+    for (;;) {
+        if (threadIdx.x == 0) s_slot = atomicAdd(P.counter, 1);
+        __syncthreads();
+        const int slot = s_slot;
+        __syncthreads();  // all have read s_slot before it is overwritten
+        if (slot >= P.njobs) break;  // the same value in every thread: uniform exit
+        const int i0 = P.job_off[slot], i1 = P.job_off[slot + 1];
+        for (int it = 0; it < iters; ++it) {
+            const bool from_user = (it & 1) == 0;
+            const double* sre = from_user ? rre : P.zre;
+            const double* sim = from_user ? rim : P.zim;
+            double* dre = from_user ? P.zre : rre;
+            double* dim = from_user ? P.zim : rim;
+            const long long pss = from_user ? psr : P.psz;
+            const long long psd = from_user ? P.psz : psr;
+            for (int i = i0; i < i1; ++i) {
+                if (P.items[3 * i + 2] != wv) continue;  // the same in every lane of the wave
+                const int b = P.items[3 * i], ch = P.items[3 * i + 1];
+                const long long co = P.coef_off[b];
+                dk_roots<K, 1, AR>(P, P.mre + co, P.mim + co, sre, sim, pss, dre, dim, psd,
+                                   P.degree[b], P.root_off[b], 64 * ch + lane);
+            }
+            __syncthreads();  // iterate t complete before t+1 reads it
+        }
+        if (iters & 1) {  // result is in the plan buffer: each wave copies its chunks back
+            for (int i = i0; i < i1; ++i) {
+                if (P.items[3 * i + 2] != wv) continue;
+                const int b = P.items[3 * i], r = 64 * P.items[3 * i + 1] + lane;
+                const long long ro = P.root_off[b];
+                if (r < P.degree[b])
+                    c_store<K>(rre, rim, psr, ro + r, c_load<K>(P.zre, P.zim, P.psz, ro + r));
+            }
+            __syncthreads();
+        }
+        if (status) {  // the wave holding chunk 0 of a polynomial checks all its roots
+            for (int i = i0; i < i1; ++i) {
+                if (P.items[3 * i + 2] != wv || P.items[3 * i + 1] != 0) continue;
+                const int b = P.items[3 * i], n = P.degree[b];
+                const long long ro = P.root_off[b];
+                int bad = 0;
+                for (int r = lane; r < n; r += 64) {
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        bad |= !isfinite(rre[c * psr + ro + r]) || !isfinite(rim[c * psr + ro + r]);
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+                if (lane == 0) status[b] = bad;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- plan ----
 
 struct DkVariant {
     int r;          // roots per lane processed together
     int waves_cu;   // resident waves per CU targeted by the grid size
+    bool packed;    // 4-wave jobs of the packed schedule (r = 1)
 };
-static const DkVariant kDkVariants[] = {{1, 8}, {2, 8}, {1, 16}, {2, 12}};
+static const DkVariant kDkVariants[] = {{1, 8, false}, {2, 8, false}, {1, 16, false},
+                                        {2, 12, false}, {1, 8, true}, {1, 12, true}};
 constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
 
 }  // namespace mpx
@@ -611,7 +699,7 @@ struct mpx_plan_s {
 
 namespace mpx {
 
-template <int K, int R, int AR>
+template <int K, int R, int AR, bool PACKED>
 static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long long psc, void* rre,
                        void* rim, long long psr, int* status, int waves_cu, hipStream_t s) {
     k_reset_counter<<<1, 1, 0, s>>>(p->d.counter);
@@ -625,8 +713,16 @@ static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long lon
                                                   (double*)rim, psr,
                                                   (p->flags & MPX_DK_INIT) ? 1 : 0);
     if ((st = launch_status())) return st;
-    k_durand_kerner<K, R, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
-                                                        (double*)rim, psr, status, p->iters);
+    if constexpr (PACKED) {
+        long long groups = (long long)p->cus * waves_cu / kDkPackedWaves;
+        if (groups > p->d.njobs) groups = p->d.njobs;
+        if (groups < 1) groups = 1;
+        k_dk_packed<K, AR><<<(unsigned)groups, 64 * kDkPackedWaves, 0, s>>>(
+            p->d, (double*)rre, (double*)rim, psr, status, p->iters);
+    } else {
+        k_durand_kerner<K, R, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
+                                                            (double*)rim, psr, status, p->iters);
+    }
     return launch_status();
 }
 
@@ -635,10 +731,12 @@ static int launch_dk(mpx_plan_s* p, int variant, const void* are, const void* ai
     const DkVariant v = kDkVariants[variant];
 #define MPX_DK_CASE(KK, AR_)                                                                   \
     if (p->K == KK && ar == AR_) {                                                             \
-        if (v.r == 1) return launch_dk_t<KK, 1, AR_>(p, are, aim, psc, rre, rim, psr, status, \
-                                                     v.waves_cu, s);                           \
-        return launch_dk_t<KK, 2, AR_>(p, are, aim, psc, rre, rim, psr, status, v.waves_cu,   \
-                                       s);                                                     \
+        if (v.packed) return launch_dk_t<KK, 1, AR_, true>(p, are, aim, psc, rre, rim, psr,   \
+                                                           status, v.waves_cu, s);             \
+        if (v.r == 1) return launch_dk_t<KK, 1, AR_, false>(p, are, aim, psc, rre, rim, psr,  \
+                                                            status, v.waves_cu, s);            \
+        return launch_dk_t<KK, 2, AR_, false>(p, are, aim, psc, rre, rim, psr, status,        \
+                                              v.waves_cu, s);                                  \
     }
     const int ar = arith_of(p->prec);
     MPX_DK_CASE(2, AR_BF)
@@ -843,6 +941,59 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     // longest-processing-time order: descending n^2 (ties: index order)
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return deg[a] > deg[b]; });
 
+    // Packed schedule for the 4-wave kernel.  A chunk (64 roots) of a degree-n
+    // polynomial costs n per sweep.  Polynomials, in LPT order, are added to
+    // the open job with each chunk going to the least-loaded wave (lowest wave
+    // on ties); a job is closed when adding the next polynomial would lift its
+    // heaviest wave above L, the largest polynomial's cost spread over the
+    // four waves.  Jobs are then ordered heaviest first.
+    std::vector<int> job_off(1, 0), items;
+    {
+        const int W = kDkPackedWaves;
+        long long L = 0;
+        for (int b = 0; b < (int)batch; ++b) {
+            const long long c = (deg[b] + 63) / 64;
+            L = std::max(L, (c + W - 1) / W * deg[b]);
+        }
+        struct Job { long long heaviest; std::vector<int> it; };
+        std::vector<Job> jobs;
+        long long load[kDkPackedWaves] = {0, 0, 0, 0};
+        std::vector<int> cur;
+        auto place = [&](int b, long long* ld, std::vector<int>& out) {
+            const int c = (deg[b] + 63) / 64;
+            for (int ch = 0; ch < c; ++ch) {
+                int w = 0;
+                for (int v = 1; v < W; ++v)
+                    if (ld[v] < ld[w]) w = v;
+                ld[w] += deg[b];
+                out.insert(out.end(), {b, ch, w});
+            }
+        };
+        auto heaviest = [&](const long long* ld) { return *std::max_element(ld, ld + W); };
+        for (int b : order) {
+            long long trial[kDkPackedWaves];
+            std::copy(load, load + W, trial);
+            std::vector<int> add;
+            place(b, trial, add);
+            if (!cur.empty() && heaviest(trial) > L) {
+                jobs.push_back({heaviest(load), cur});
+                cur.clear();
+                std::fill(trial, trial + W, 0LL);
+                add.clear();
+                place(b, trial, add);
+            }
+            std::copy(trial, trial + W, load);
+            cur.insert(cur.end(), add.begin(), add.end());
+        }
+        if (!cur.empty()) jobs.push_back({heaviest(load), cur});
+        std::stable_sort(jobs.begin(), jobs.end(),
+                         [](const Job& a, const Job& b) { return a.heaviest > b.heaviest; });
+        for (const Job& j : jobs) {
+            items.insert(items.end(), j.it.begin(), j.it.end());
+            job_off.push_back((int)(items.size() / 3));
+        }
+    }
+
     auto* p = new (std::nothrow) mpx_plan_s();
     if (!p) return MPX_EINVAL;
     p->prec = prec;
@@ -862,8 +1013,10 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     const size_t sz_off = (n_i + 1) * sizeof(long long);
     const size_t sz_m = 2 * K * (size_t)std::max<long long>(p->total_coef, 1) * sizeof(double);
     const size_t sz_z = 2 * K * (size_t)std::max<long long>(p->total_roots, 1) * sizeof(double);
+    const size_t sz_jo = job_off.size() * sizeof(int), sz_it = std::max<size_t>(items.size(), 1) * sizeof(int);
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t total = al(sz_order) + al(sz_deg) + 2 * al(sz_off) + al(sz_m) + al(sz_z) + 256;
+    const size_t total = al(sz_order) + al(sz_deg) + 2 * al(sz_off) + al(sz_m) + al(sz_z) + 256 +
+                         al(sz_jo) + al(sz_it);
     if (hipMalloc(&p->dev, total) != hipSuccess) { delete p; return MPX_EDEVICE; }
     char* c = (char*)p->dev;
     auto take = [&](size_t v) { char* r = c; c += al(v); return r; };
@@ -874,6 +1027,8 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     double* d_m = (double*)take(sz_m);
     double* d_z = (double*)take(sz_z);
     int* d_cnt = (int*)take(256);
+    int* d_jo = (int*)take(sz_jo);
+    int* d_it = (int*)take(sz_it);
     hipError_t e = hipSuccess;
     if (batch > 0) {
         e = hipMemcpy(d_order, order.data(), sz_order, hipMemcpyHostToDevice);
@@ -881,11 +1036,14 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     }
     if (e == hipSuccess) e = hipMemcpy(d_coff, coff.data(), sz_off, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_roff, roff.data(), sz_off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_jo, job_off.data(), sz_jo, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(d_it, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(p->dev); delete p; return MPX_EDEVICE; }
     const long long psm = std::max<long long>(p->total_coef, 1);
     const long long psz = std::max<long long>(p->total_roots, 1);
     p->d = DkPlanDev{d_order, d_deg, d_coff, d_roff, d_m, d_m + K * psm, d_z, d_z + K * psz,
-                     d_cnt, psm, psz};
+                     d_cnt, psm, psz, d_jo, d_it, (int)(job_off.size() - 1)};
     *out = p;
     return MPX_OK;
 }

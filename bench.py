@@ -471,7 +471,7 @@ def dk_row(mpx, torch, T):
     mpx.RootsPlan("qd", deg, iters=0, init=True, graph=False).run(gcr, gci, zr, zi)
     z0r, z0i = zr.clone(), zi.clone()
     plan = mpx.RootsPlan("qd", deg, iters=200, init=False, graph=True)
-    variant, probe_ms = plan.autotune(gcr, gci, z0r, z0i, iters_probe=2)
+    variant, probe_ms = plan.autotune(gcr, gci, z0r, z0i, iters_probe=8)
     stream = torch.cuda.Stream()
     st = torch.zeros(deg.size, dtype=torch.int32, device="cuda")
     times = []

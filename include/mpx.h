@@ -345,7 +345,8 @@ int mpx_plan_destroy(mpx_plan plan);
 /* Launch-shape variants (roots per lane, resident waves per CU, or the packed
  * schedule: 4-wave jobs built by the plan, each holding whole polynomials
  * whose 64-root chunks are spread over the waves to balance their loads);
- * results do not depend on the variant.  The autotuner runs each for iters_probe sweeps
+ * results do not depend on the variant.  A new plan uses the packed schedule
+ * with 8 resident waves per CU.  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants
  * (a variant's time is its faster round), keeps the fastest in the plan
  * and returns its index (or a negative status).  Synchronises; allocates. */

@@ -683,7 +683,7 @@ constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
 struct mpx_plan_s {
     int prec = 0, K = 0, batch = 0, iters = 0;
     unsigned flags = 0;
-    int variant = 1;
+    int variant = 4;                // the packed schedule, 8 waves per CU (kDkVariants[4])
     long long total_coef = 0, total_roots = 0;
     int cus = 256;
     void* dev = nullptr;            // one allocation: schedule + offsets + buffers
@@ -946,7 +946,9 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     // the open job with each chunk going to the least-loaded wave (lowest wave
     // on ties); a job is closed when adding the next polynomial would lift its
     // heaviest wave above L, the largest polynomial's cost spread over the
-    // four waves.  Jobs are then ordered heaviest first.
+    // four waves.  Before it is closed, its lighter waves take the smallest
+    // polynomials not yet placed, as long as its heaviest wave does not grow.
+    // Jobs are then ordered heaviest first.
     std::vector<int> job_off(1, 0), items;
     {
         const int W = kDkPackedWaves;
@@ -959,6 +961,7 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
         std::vector<Job> jobs;
         long long load[kDkPackedWaves] = {0, 0, 0, 0};
         std::vector<int> cur;
+        std::vector<char> placed(batch, 0);
         auto place = [&](int b, long long* ld, std::vector<int>& out) {
             const int c = (deg[b] + 63) / 64;
             for (int ch = 0; ch < c; ++ch) {
@@ -970,22 +973,41 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
             }
         };
         auto heaviest = [&](const long long* ld) { return *std::max_element(ld, ld + W); };
+        auto close = [&]() {
+            const long long H = heaviest(load);
+            for (int k = (int)batch - 1; k >= 0; --k) {  // smallest polynomials first
+                const int b = order[k];
+                if (placed[b]) continue;
+                long long trial[kDkPackedWaves];
+                std::copy(load, load + W, trial);
+                std::vector<int> add;
+                place(b, trial, add);
+                if (heaviest(trial) > H) break;
+                placed[b] = 1;
+                std::copy(trial, trial + W, load);
+                cur.insert(cur.end(), add.begin(), add.end());
+            }
+            jobs.push_back({heaviest(load), cur});
+            cur.clear();
+            std::fill(load, load + W, 0LL);
+        };
         for (int b : order) {
+            if (placed[b]) continue;
             long long trial[kDkPackedWaves];
             std::copy(load, load + W, trial);
             std::vector<int> add;
             place(b, trial, add);
             if (!cur.empty() && heaviest(trial) > L) {
-                jobs.push_back({heaviest(load), cur});
-                cur.clear();
+                close();
                 std::fill(trial, trial + W, 0LL);
                 add.clear();
                 place(b, trial, add);
             }
+            placed[b] = 1;
             std::copy(trial, trial + W, load);
             cur.insert(cur.end(), add.begin(), add.end());
         }
-        if (!cur.empty()) jobs.push_back({heaviest(load), cur});
+        if (!cur.empty()) close();
         std::stable_sort(jobs.begin(), jobs.end(),
                          [](const Job& a, const Job& b) { return a.heaviest > b.heaviest; });
         for (const Job& j : jobs) {

@@ -457,20 +457,12 @@ k_gemm_batched(int nitems, const GbItem* __restrict__ items, const GbProb* __res
 // k are issued before their multiply-adds.  Lanes outside the problem read a
 // clamped (valid) row / column and store nothing.
 template <typename T, int K, int U, int AR>
-__global__ void __launch_bounds__(kGemmThreads)
-k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
-                    const GbProb* __restrict__ probs, const T* __restrict__ A, long long psA,
-                    const T* __restrict__ B, long long psB, T* __restrict__ C, long long psC,
-                    int* counter) {
+__device__ __forceinline__ void wave_tile(const GbItem& w, const GbProb& q, const T* __restrict__ A,
+                                          long long psA, const T* __restrict__ B, long long psB,
+                                          T* __restrict__ C, long long psC) {
     const int lane = threadIdx.x & 63;
     const int lr = lane >> 3, lc = lane & 7;
-    for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(counter, 1);
-        it = __shfl(it, 0, 64);
-        if (it >= nitems) break;  // the same value in every lane: uniform exit
-        const GbItem w = items[it];
-        const GbProb q = probs[w.p];
+    {
         const int row = w.m0 + lr, col = w.n0 + lc;
         const long long ar = (long long)(row < q.m ? row : q.m - 1) * q.k;
         const long long bc = col < q.n ? col : q.n - 1;
@@ -495,11 +487,67 @@ k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
     }
 }
 
+template <typename T, int K, int U, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
+                    const GbProb* __restrict__ probs, const T* __restrict__ A, long long psA,
+                    const T* __restrict__ B, long long psB, T* __restrict__ C, long long psC,
+                    int* counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1);
+        it = __shfl(it, 0, 64);
+        if (it >= nitems) break;  // the same value in every lane: uniform exit
+        const GbItem w = items[it];
+        wave_tile<T, K, U, AR>(w, probs[w.p], A, psA, B, psB, C, psC);
+    }
+}
+
+// Mixed tiling: the interior of each product in 16 TM x 16 TN workgroup
+// tiles and its ragged edges in 8 x 8 wave tiles.  A work unit is four
+// consecutive items: a workgroup tile (item 1 has p = kGbTileUnit, items 2
+// and 3 unused) or up to four wave tiles, one per wave (p = -1: none).  The
+// unit kind is read by the whole workgroup, so the barriers inside the
+// workgroup tile are reached by every thread.
+constexpr int kGbTileUnit = -2;
+
+template <typename T, int K, int TM, int TN, int BK, int U, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm_batched_mixed(int nunits, const GbItem* __restrict__ items,
+                     const GbProb* __restrict__ probs, const T* __restrict__ A, long long psA,
+                     const T* __restrict__ B, long long psB, T* __restrict__ C, long long psC,
+                     int* counter) {
+    __shared__ T sA[K][BK][16 * TM];
+    __shared__ T sB[K][BK][16 * TN];
+    __shared__ int next;
+    const int wv = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = next;
+        __syncthreads();  // all have read `next` before it is overwritten
+        if (u >= nunits) break;  // the same value in every thread: uniform exit
+        const GbItem* unit = items + 4LL * u;
+        if (unit[1].p == kGbTileUnit) {
+            const GbItem w = unit[0];
+            const GbProb q = probs[w.p];
+            gemm_tile<T, K, TM, TN, BK, false, false, AR>(q.m, q.n, q.k, A + q.a, q.k, psA,
+                                                          B + q.b, q.n, psB, C + q.c, q.n, psC,
+                                                          w.m0, w.n0, sA, sB);
+        } else {
+            const GbItem w = unit[wv];
+            if (w.p >= 0) wave_tile<T, K, U, AR>(w, probs[w.p], A, psA, B, psB, C, psC);
+        }
+    }
+}
+
 struct GbVariant {
     int (*launch)(int nitems, const GbItem*, const GbProb*, const void*, long long, const void*,
                   long long, void*, long long, int*, int grid, hipStream_t);
     int bm, bn;
     int per_wg;  // items a workgroup runs at once (4 for wave tiles)
+    bool mixed;  // work units of the mixed tiling (bm x bn interior, 8 x 8 edges)
 };
 
 template <typename T, int K, int TM, int TN, int BK, int AR>
@@ -508,6 +556,15 @@ static int gb_launch(int nitems, const GbItem* items, const GbProb* probs, const
                      int* counter, int grid, hipStream_t s) {
     k_gemm_batched<T, K, TM, TN, BK, AR><<<grid, kGemmThreads, 0, s>>>(
         nitems, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
+    return launch_status();
+}
+
+template <typename T, int K, int TM, int TN, int BK, int U, int AR>
+static int gb_launch_mixed(int nunits, const GbItem* items, const GbProb* probs, const void* A,
+                           long long psA, const void* B, long long psB, void* C, long long psC,
+                           int* counter, int grid, hipStream_t s) {
+    k_gemm_batched_mixed<T, K, TM, TN, BK, U, AR><<<grid, kGemmThreads, 0, s>>>(
+        nunits, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
     return launch_status();
 }
 
@@ -524,15 +581,18 @@ static int gb_launch_wave(int nitems, const GbItem* items, const GbProb* probs, 
 // smallest tiles first (small problems need many tiles to fill the chip, and
 // small tiles waste less on ragged edges).
 static std::vector<GbVariant> gb_variants(int prec) {
-#define MPX_GB(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_>, 16 * TM_, 16 * TN_, 1}
-#define MPX_GBW(T_, K_, U_, AR_) GbVariant{gb_launch_wave<T_, K_, U_, AR_>, 8, 8, kGemmThreads / 64}
+#define MPX_GB(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_>, 16 * TM_, 16 * TN_, 1, false}
+#define MPX_GBW(T_, K_, U_, AR_) GbVariant{gb_launch_wave<T_, K_, U_, AR_>, 8, 8, kGemmThreads / 64, false}
+#define MPX_GBM(T_, K_, TM_, TN_, BK_, U_, AR_) \
+    GbVariant{gb_launch_mixed<T_, K_, TM_, TN_, BK_, U_, AR_>, 16 * TM_, 16 * TN_, 1, true}
     switch (prec) {
         case MPX_DD: return {MPX_GBW(double, 2, 4, AR_BF), MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF)};
-        case MPX_TD: return {MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
-        case MPX_QD: return {MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
+        case MPX_TD: return {MPX_GBM(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
+        case MPX_QD: return {MPX_GBM(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
         case MPX_FF: return {MPX_GBW(float, 2, 4, AR_BF), MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF)};
         default: return {};
     }
+#undef MPX_GBM
 #undef MPX_GBW
 #undef MPX_GB
 }
@@ -578,24 +638,56 @@ extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count
     // work items of every variant, longest k first (ties: problem, tile order)
     std::vector<GbItem> all;
     for (const auto& v : p->vars) {
-        long long nit = 0;
+        long long nit = 0;  // items (tiles; for the mixed tiling at most 4 items per tile or edge tile)
         for (int64_t i = 0; i < count; ++i)
-            nit += ceil_div(probs[i].m, v.bm) * ceil_div(probs[i].n, v.bn);
+            nit += (v.mixed ? 4 * ceil_div(probs[i].m, 8) * ceil_div(probs[i].n, 8)
+                            : ceil_div(probs[i].m, v.bm) * ceil_div(probs[i].n, v.bn));
         if (nit > INT32_MAX / 2) {  // the work counter is an int
             delete p;
             return MPX_ENOTSUP;
         }
     }
+    auto by_k = [&](const GbItem& a, const GbItem& b) { return probs[a.p].k > probs[b.p].k; };
     for (const auto& v : p->vars) {
         std::vector<GbItem> items;
-        for (int64_t i = 0; i < count; ++i)
-            for (int r = 0; r < probs[i].m; r += v.bm)
-                for (int c = 0; c < probs[i].n; c += v.bn) items.push_back(GbItem{(int)i, r, c});
-        std::stable_sort(items.begin(), items.end(), [&](const GbItem& a, const GbItem& b) {
-            return probs[a.p].k > probs[b.p].k;
-        });
+        int nunits = 0;
+        if (!v.mixed) {
+            for (int64_t i = 0; i < count; ++i)
+                for (int r = 0; r < probs[i].m; r += v.bm)
+                    for (int c = 0; c < probs[i].n; c += v.bn) items.push_back(GbItem{(int)i, r, c});
+            std::stable_sort(items.begin(), items.end(), by_k);
+            nunits = (int)items.size();
+        } else {
+            // interior bm x bn tiles over [0, fm) x [0, fn); 8 x 8 edge tiles over
+            // the rest; units of one tile or four edge tiles, longest k first
+            std::vector<GbItem> tiles, edges;
+            for (int64_t i = 0; i < count; ++i) {
+                const int m = probs[i].m, n = probs[i].n;
+                const int fm = m / v.bm * v.bm, fn = n / v.bn * v.bn;
+                for (int r = 0; r < fm; r += v.bm)
+                    for (int c = 0; c < fn; c += v.bn) tiles.push_back(GbItem{(int)i, r, c});
+                for (int r = fm; r < m; r += 8)
+                    for (int c = 0; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
+                for (int r = 0; r < fm; r += 8)
+                    for (int c = fn; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
+            }
+            std::stable_sort(tiles.begin(), tiles.end(), by_k);
+            std::stable_sort(edges.begin(), edges.end(), by_k);
+            const GbItem none{-1, 0, 0}, tile_mark{kGbTileUnit, 0, 0};
+            size_t a = 0, e = 0;
+            while (a < tiles.size() || e < edges.size()) {
+                const bool take_tile = e >= edges.size() ||
+                                       (a < tiles.size() && probs[tiles[a].p].k >= probs[edges[e].p].k);
+                if (take_tile) {
+                    items.insert(items.end(), {tiles[a++], tile_mark, none, none});
+                } else {
+                    for (int w = 0; w < 4; ++w) items.push_back(e < edges.size() ? edges[e++] : none);
+                }
+                ++nunits;
+            }
+        }
         p->item_off.push_back((long long)all.size());
-        p->nitems.push_back((int)items.size());
+        p->nitems.push_back(nunits);
         all.insert(all.end(), items.begin(), items.end());
     }
     const size_t sz_p = std::max<size_t>(probs.size(), 1) * sizeof(GbProb);

@@ -241,7 +241,11 @@ struct Variant {
     {run_variant<double, 4, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"}
 
 static const std::vector<Variant>& variants(int prec) {
-    static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd")};
+    // DD also offers 16 x 32 and 16 x 16 tiles: at n = 512 the 32 x 32 tile
+    // leaves one workgroup per CU
+    static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd"),
+                                            {run_variant<double, 2, 1, 2, 16, AR_BF>, 16, 32, "dd_1x2_k16"},
+                                            {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td")};
     static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
     static const std::vector<Variant> ff = {

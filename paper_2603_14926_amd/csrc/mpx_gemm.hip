@@ -246,7 +246,8 @@ static const std::vector<Variant>& variants(int prec) {
     static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd"),
                                             {run_variant<double, 2, 1, 2, 16, AR_BF>, 16, 32, "dd_1x2_k16"},
                                             {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"}};
-    static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td")};
+    static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
+                                            {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"}};
     static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
     static const std::vector<Variant> ff = {
         {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},

@@ -1047,7 +1047,7 @@ static void dk_monic(int K, int64_t n, const double *are, const double *aim,
 /* Aberth initial values (equation for z_i^(0)): centre -c_{n-1}/n, radius
  * r = max_i |n_nz c_i|^(1/(n-i)), angles 2(i-1)pi/n + 3/(2n).  Evaluated in
  * binary64 on the leading components; lower components start at zero. */
-static void dk_aberth(int K, int64_t n, const cmp *c, cmp *z) {
+static void dk_aberth(int64_t n, const cmp *c, cmp *z) {
     int64_t nnz = 0;
     for (int64_t i = 0; i < n; i++)
         if (c[i].re[0] != 0.0 || c[i].im[0] != 0.0) nnz++;
@@ -1120,7 +1120,7 @@ void orc_polyroots(int K, int64_t batch, const int32_t *deg, const int64_t *coef
         cmp *z = (cmp *)calloc((size_t)n, sizeof(cmp));
         cmp *zn = (cmp *)calloc((size_t)n, sizeof(cmp));
         dk_monic(K, n, are, aim, psc, coef_off[b], c);
-        if (flags & 1) dk_aberth(K, n, c, z);
+        if (flags & 1) dk_aberth(n, c, z);
         else
             for (int64_t i = 0; i < n; i++) load_c(K, zre, zim, psr, root_off[b] + i, &z[i]);
         for (int it = 0; it < iters; it++) {

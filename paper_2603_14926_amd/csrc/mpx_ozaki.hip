@@ -152,7 +152,7 @@ k_oz_split_b(long long k, long long n, const double* __restrict__ B, long long l
 // k rows a wave reads at once fall in different bank halves.
 template <int S, int TA, int TB, int OZ_KT>
 __global__ void __launch_bounds__(OZ_THREADS)
-k_oz_gemm(long long m, long long n, long long k, long long mp, long long np, long long kp,
+k_oz_gemm(long long m, long long n, long long mp, long long np, long long kp,
           const double* __restrict__ SA, const double* __restrict__ SB,
           const int* __restrict__ e, const int* __restrict__ f, int beta, long long kblk,
           double* __restrict__ C, long long ldc, long long psC, int tiles_n) {
@@ -375,10 +375,10 @@ static int oz_run(long long m, long long n, long long k, const double* A, long l
     const int tn = (int)(d.np / 32), tm = (int)(d.mp / (32 * TA));
     if (g_oz_variant.load(std::memory_order_relaxed) == 1)
         k_oz_gemm<S, TA, 1, 16><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
-            m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
+            m, n, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
     else
         k_oz_gemm<S, TA, 1, 8><<<(unsigned)(tn * tm), OZ_THREADS, 0, s>>>(
-            m, n, k, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
+            m, n, d.mp, d.np, d.kp, SA, SB, e, f, beta, kblk, C, ldc, psC, tn);
     return launch_status();
 }
 

@@ -243,6 +243,25 @@ def cgemm_3m(K, Are, Aim, Bre, Bim):
     return Cre, Cim
 
 
+def cgemm_3m_entries(K, Are, Aim, Bre, Bim, rows, cols):
+    """Selected entries (rows[t], cols[t]) of the 3M complex product, by the
+    steps of cgemm_3m restricted to those entries: the operand sums
+    Are + Aim and Bre + Bim, the three real products C1 = Are Bre,
+    C2 = Aim Bim, C3 = (Are + Aim)(Bre + Bim), then Re = C1 - C2 and
+    Im = (C3 - C1) - C2.  Returns (re, im), each (K, len(rows))."""
+    Are, Aim, Bre, Bim = (_chk(v, K) for v in (Are, Aim, Bre, Bim))
+    SA = add(K, Are.reshape(K, -1), Aim.reshape(K, -1)).reshape(Are.shape)
+    SB = add(K, Bre.reshape(K, -1), Bim.reshape(K, -1)).reshape(Bre.shape)
+    c1 = gemm_entries(K, Are, Bre, rows, cols)
+    c2 = gemm_entries(K, Aim, Bim, rows, cols)
+    c3 = gemm_entries(K, SA, SB, rows, cols)
+    re = np.zeros_like(c1); im = np.zeros_like(c1)
+    for t in range(c1.shape[1]):
+        re[:, t] = op1(K, "add", c1[:, t], -c2[:, t])
+        im[:, t] = op1(K, "add", op1(K, "add", c3[:, t], -c1[:, t]), -c2[:, t])
+    return re, im
+
+
 # ------------------------------------------------------------ float-float ----
 
 def ff_add(x, y):

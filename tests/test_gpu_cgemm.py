@@ -59,3 +59,20 @@ def test_cgemm_3m_paper_accuracy_1024(p, K):
             scale[part] = max(scale[part], abs(float(ex)))
     digits = min(-math.log10(worst[q] / scale[q]) if worst[q] else 99.0 for q in worst)
     assert digits >= PAPER_COMPLEX_DIGITS[K], digits
+
+
+@pytest.mark.parametrize("n", [2048, 2049])
+def test_cgemm_3m_bench_size_sampled_bit_exact(n):
+    """The benchmark sizes (QD, n = 2048 and the paper's 2049): sampled
+    entries, tile edges and corners included, bit-exact against the oracle's
+    3M steps evaluated entry by entry."""
+    K = 4
+    Are, Aim = _cx(K, (n, n), 70)
+    Bre, Bim = _cx(K, (n, n), 72)
+    gr, gi = mpx.cgemm_3m("qd", to_gpu(Are), to_gpu(Aim), to_gpu(Bre), to_gpu(Bim))
+    rng = np.random.default_rng(n)
+    rows = np.concatenate([[0, 0, n - 1, n - 1, 31, 32, n // 2], rng.integers(0, n, 13)])
+    cols = np.concatenate([[0, n - 1, 0, n - 1, 32, 31, n // 2 + 1], rng.integers(0, n, 13)])
+    wr, wi = oracle.cgemm_3m_entries(K, Are, Aim, Bre, Bim, rows, cols)
+    assert bits_equal(np.ascontiguousarray(to_np(gr)[:, rows, cols]), wr)
+    assert bits_equal(np.ascontiguousarray(to_np(gi)[:, rows, cols]), wi)

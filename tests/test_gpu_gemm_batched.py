@@ -104,3 +104,32 @@ def test_batched_argument_errors():
         plan.run(small, small, small)        # C needs 16 elements per plane
     with pytest.raises(mpx.MpxError):
         plan.set_variant(99)
+
+
+def test_batched_bench_configuration_sampled():
+    """The benchmark's batch: 4096 QD products, m, n, k uniform in [16, 128],
+    every tiling; 12 products (the extremes of m, n and k among them) checked
+    whole against the oracle's GEMM."""
+    K, count = 4, 4096
+    rng = np.random.default_rng(synth.seed_for(1, 50))
+    ms, ns, ks = (rng.integers(16, 129, count) for _ in range(3))
+    plan = mpx.GemmBatchPlan("qd", ms, ns, ks)
+    a_off, b_off, c_off, (ta, tb, tc) = plan.offsets()
+    A_np = synth.mp_array(K, int(ta), 81, "U")
+    B_np = synth.mp_array(K, int(tb), 82, "U")
+    A, B = to_gpu(A_np), to_gpu(B_np)
+    pick = sorted({int(np.argmax(ms)), int(np.argmin(ms)), int(np.argmax(ns)), int(np.argmin(ns)),
+                   int(np.argmax(ks)), int(np.argmin(ks)), 0, count - 1,
+                   *rng.integers(0, count, 4).tolist()})
+    want = {}
+    for i in pick:
+        Ai = np.ascontiguousarray(A_np[:, a_off[i]:a_off[i] + ms[i] * ks[i]].reshape(K, ms[i], ks[i]))
+        Bi = np.ascontiguousarray(B_np[:, b_off[i]:b_off[i] + ks[i] * ns[i]].reshape(K, ks[i], ns[i]))
+        want[i] = oracle.gemm(K, Ai, Bi)
+    for v in range(plan.variant_count()):
+        plan.set_variant(v)
+        Cm = torch.full((K, int(tc)), float("nan"), dtype=torch.float64, device="cuda")
+        got = to_np(plan.run(A, B, Cm))
+        for i in pick:
+            g = np.ascontiguousarray(got[:, c_off[i]:c_off[i] + ms[i] * ns[i]].reshape(K, ms[i], ns[i]))
+            assert bits_equal(g, want[i]), (v, i)

@@ -211,3 +211,16 @@ def test_cgemm_3m_matches_definition_and_paper_digits(K):
                 scale[part] = max(scale[part], abs(float(ex)))
     digits = min(-math.log10(worst[p] / scale[p]) if worst[p] else 99.0 for p in worst)
     assert digits >= PAPER_COMPLEX_DIGITS[K], (K, digits)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_cgemm_3m_entries_match_the_whole_product(K):
+    """The entry-wise 3M evaluation (used at sizes where the whole product is
+    too slow for the oracle) reproduces the whole-matrix one bit for bit."""
+    Are, Aim = synth.mp_array(K, (9, 13), 60, "W"), synth.mp_array(K, (9, 13), 61, "W")
+    Bre, Bim = synth.mp_array(K, (13, 7), 62, "W"), synth.mp_array(K, (13, 7), 63, "W")
+    Cre, Cim = oracle.cgemm_3m(K, Are, Aim, Bre, Bim)
+    rows, cols = np.divmod(np.arange(9 * 7), 7)
+    re, im = oracle.cgemm_3m_entries(K, Are, Aim, Bre, Bim, rows, cols)
+    assert np.array_equal(re.view(np.uint64), Cre.reshape(K, -1).view(np.uint64))
+    assert np.array_equal(im.view(np.uint64), Cim.reshape(K, -1).view(np.uint64))

@@ -165,7 +165,8 @@ def test_dk_full_batch_sampled_bit_exact():
 
 
 @pytest.mark.parametrize("p,K", PRECS)
-@pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023), (8, 2047)])
+@pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023), (8, 2047),
+                                       (1024, 2047)])
 def test_estrin_bit_exact(p, K, batch, deg):
     coef = synth.mp_array(K, (batch, deg + 1), 80 + deg, "U")
     x = synth.mp_array(K, batch, 81 + deg, "U")
@@ -182,7 +183,8 @@ def test_estrin_rejects_degree_beyond_2047():
 
 
 @pytest.mark.parametrize("p,K", PRECS)
-@pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023)])
+@pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023),
+                                       (1024, 1023)])
 def test_polyval_cplx_bit_exact(p, K, batch, deg):
     """Real-coefficient polynomials at complex points, Horner and Estrin."""
     coef = synth.mp_array(K, (batch, deg + 1), 90 + deg, "U")

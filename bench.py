@@ -694,28 +694,43 @@ def main():
     }
     del A, B, Cm
     if not args.quick:
+        def gemm_rows():
+            g = {}
+            for q in ("qd", "td", "dd"):
+                for nn in (512, 1024, 2048):
+                    g[f"{q}_{nn}"] = gemm_row(mpx, torch, T, q, nn, reps=5 if nn < 2048 else 3)
+            g["ff_2048"] = gemm_row(mpx, torch, T, "ff", 2048, reps=3)
+            return g
+        plan = [("gemm", gemm_rows),
+                ("gemv_8192", lambda: gemv_rows(mpx, torch, T)),
+                ("vector", lambda: vector_rows(mpx, torch, T)),
+                ("cgemm_3m", lambda: cgemm_rows(mpx, torch, T)),
+                ("polyeval", lambda: polyeval_rows(mpx, torch, T)),
+                ("bf_vs_nobf", lambda: nobf_rows(mpx, torch, T)),
+                ("strassen", lambda: strassen_rows(mpx, torch, T)),
+                ("batched_gemm", lambda: batched_gemm_rows(mpx, torch, T)),
+                ("durand_kerner", lambda: dk_row(mpx, torch, T)),
+                ("autograd", lambda: autograd_row(mpx, torch, T)),
+                ("ozaki", lambda: ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192)))]
         rows = {}
-        log("gemm rows")
-        g = {}
-        for q in ("qd", "td", "dd"):
-            for nn in (512, 1024, 2048):
-                g[f"{q}_{nn}"] = gemm_row(mpx, torch, T, q, nn, reps=5 if nn < 2048 else 3)
-        g["ff_2048"] = gemm_row(mpx, torch, T, "ff", 2048, reps=3)
-        rows["gemm"] = g
-        log("gemv rows"); rows["gemv_8192"] = gemv_rows(mpx, torch, T)
-        log("vector rows"); rows["vector"] = vector_rows(mpx, torch, T)
-        log("complex 3M"); rows["cgemm_3m"] = cgemm_rows(mpx, torch, T)
-        log("horner vs estrin"); rows["polyeval"] = polyeval_rows(mpx, torch, T)
-        log("bf vs nobf"); rows["bf_vs_nobf"] = nobf_rows(mpx, torch, T)
-        log("strassen"); rows["strassen"] = strassen_rows(mpx, torch, T)
-        log("batched gemm"); rows["batched_gemm"] = batched_gemm_rows(mpx, torch, T)
-        log("durand-kerner"); rows["durand_kerner"] = dk_row(mpx, torch, T)
-        log("autograd"); rows["autograd"] = autograd_row(mpx, torch, T)
-        rows["ozaki"] = ozaki_row(mpx, torch, T, (4096,) if args.no_8192 else (4096, 8192))
+        for i, (name, fn) in enumerate(plan):
+            log(f"row {name}")
+            try:
+                rows[name] = fn()
+            except Exception as e:
+                # the headline is already measured: record the failure, run no
+                # further GPU work after it, and still print the line
+                rows[name] = {"error": f"{type(e).__name__}: {e}"}
+                rows["skipped_after_error"] = [nm for nm, _ in plan[i + 1:]]
+                log(f"row {name} failed ({type(e).__name__}: {e}); remaining rows skipped")
+                break
         out["rows"] = rows
     if not args.no_cpu and not args.quick and p != "ff":
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(p, n)
+        try:
+            out["cpu_baseline"] = cpu_baseline(p, n)
+        except Exception as e:  # the line is printed regardless
+            out["cpu_baseline"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out), flush=True)
 
 

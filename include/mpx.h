@@ -332,9 +332,11 @@ int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef,
  * coincident start values).
  *
  * A plan is created outside graph capture; it allocates its device schedule
- * (polynomials in descending-degree order for load balance) and working
- * buffers (monic coefficients, second iterate) and frees them in
- * mpx_plan_destroy.  With MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots
+ * (polynomials in descending-degree order for load balance, and the packed
+ * 4-wave jobs) and working buffers (monic coefficients, second iterate) and
+ * frees them in mpx_plan_destroy.  The constructor returns MPX_EINVAL for a
+ * degree below 1 or unknown flags, MPX_ENOTSUP when the batch holds more than
+ * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when allocation fails.  With MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots
  * captures its launches into a HIP graph on first use and replays it while
  * buffers and stream stay the same.  One persistent launch processes the
  * whole batch.  Calls on one plan must not overlap. */

@@ -1010,6 +1010,9 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
         if (!cur.empty()) close();
         std::stable_sort(jobs.begin(), jobs.end(),
                          [](const Job& a, const Job& b) { return a.heaviest > b.heaviest; });
+        size_t n_items = 0;
+        for (const Job& j : jobs) n_items += j.it.size() / 3;
+        if (n_items > (size_t)(INT32_MAX / 4)) return MPX_ENOTSUP;  // int job offsets and indices
         for (const Job& j : jobs) {
             items.insert(items.end(), j.it.begin(), j.it.end());
             job_off.push_back((int)(items.size() / 3));

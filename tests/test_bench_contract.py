@@ -1,0 +1,55 @@
+"""CPU checks of bench.py's contract: one GPU only (more exits with a
+message), the HBM-traffic figure is taken only from counters recorded on the
+current kernel sources, and the CPU baseline leg reports the oracle with the
+fields the JSON line carries."""
+import importlib.util
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""            # no JSON line for an unmeasured N
+
+
+def test_traffic_only_from_counters_on_current_sources(tmp_path):
+    bench = _bench()
+    rec = json.load(open(os.path.join(ROOT, "profiles", "qd_gemm_2048_counters.json")))
+    assert "paper_2603_14926_amd/csrc/mpx_gemm.hip" in rec["sources"]
+    assert bench.measured_traffic("qd_gemm_2048") == rec["traffic_bytes"]
+    assert bench.measured_traffic("no_such_workload") is None
+    # a copy of the tree whose GEMM source differs by one byte: no traffic
+    os.makedirs(tmp_path / "profiles")
+    shutil.copy(os.path.join(ROOT, "profiles", "qd_gemm_2048_counters.json"), tmp_path / "profiles")
+    for f in rec["sources"]:
+        dst = tmp_path / f
+        os.makedirs(dst.parent, exist_ok=True)
+        shutil.copy(os.path.join(ROOT, f), dst)
+    bench.ROOT = str(tmp_path)
+    assert bench.measured_traffic("qd_gemm_2048") == rec["traffic_bytes"]
+    with open(tmp_path / rec["sources"][0], "ab") as fh:
+        fh.write(b"\n")
+    assert bench.measured_traffic("qd_gemm_2048") is None
+
+
+def test_cpu_baseline_fields():
+    bench = _bench()
+    r = bench.cpu_baseline("qd", 64, target_s=0.05)
+    assert r["kind"] == "oracle" and r["unit"] == "mp-op/s"
+    assert r["value"] > 0 and 1 <= r["cores"] <= 16
+    assert "QD GEMM rows 0.." in r["sample"] and "64x64x64" in r["sample"]

@@ -154,6 +154,20 @@ def _planes(t: torch.Tensor, p, nd: int, name: str):
     return t.stride(0), t.stride(1)
 
 
+def _expect(t: torch.Tensor, shape, name: str):
+    """An output (or an operand sized by the others) must have exactly the
+    result's shape: the library writes the whole extent, so a smaller view
+    would be written past its end."""
+    if tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError(f"{name}: expected shape {tuple(int(v) for v in shape)}, got {tuple(t.shape)}")
+
+
+def _same_layout(t: torch.Tensor, ref: torch.Tensor, name: str, ref_name: str):
+    """Real / imaginary parts share one plane stride and leading dimension."""
+    if t.shape != ref.shape or t.stride() != ref.stride():
+        raise ValueError(f"{name} must match {ref_name}'s shape and strides")
+
+
 def workspace(op: int, p, m: int, n: int = 0, k: int = 0, extra: int = 0) -> torch.Tensor:
     nbytes = int(lib().mpx_workspace_size(op, prec_of(p), m, n, k, extra))
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
@@ -171,6 +185,7 @@ def _ew(fn, p, x, y, out):
     if out is None:
         out = torch.empty_like(x)
     psz, _ = _planes(out, p, 1, "out")
+    _expect(out, (ncomp(p), n), "out")
     _check(fn(p, n, _ptr(x), psx, _ptr(y), psy, _ptr(out), psz, _stream()), fn.__name__)
     return out
 
@@ -210,6 +225,9 @@ def dot(p, x, y, out=None, ws=None):
         raise ValueError("x and y lengths differ")
     if out is None:
         out = torch.empty(ncomp(p), dtype=dtype_of(p), device=x.device)
+    _expect(out, (ncomp(p),), "out")
+    if out.dtype != dtype_of(p) or not out.is_cuda or (out.numel() > 1 and out.stride(0) != 1):
+        raise ValueError("out: expected K contiguous GPU values of the precision's dtype")
     if ws is None:
         ws = workspace(OP_DOT, p, n)
     _check(lib().mpx_dot(p, n, _ptr(x), psx, _ptr(y), psy, _ptr(out), _ptr(ws), ws.numel(),
@@ -229,6 +247,7 @@ def gemv(p, A, x, trans=False, out=None, ws=None):
     if out is None:
         out = torch.empty((ncomp(p), rows), dtype=dtype_of(p), device=A.device)
     psy, _ = _planes(out, p, 1, "out")
+    _expect(out, (ncomp(p), rows), "out")
     if ws is None:
         ws = workspace(OP_GEMV, p, m, n, int(trans))
     _check(lib().mpx_gemv(p, int(trans), m, n, _ptr(A), max(lda, n), psA, _ptr(x), psx,
@@ -255,6 +274,7 @@ def gemm(p, A, B, transA=False, transB=False, out=None, variant=None):
     if out is None:
         out = torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=A.device)
     psC, ldc = _planes(out, p, 2, "out")
+    _expect(out, (ncomp(p), m, n), "out")
     lda = max(lda, A.shape[2]); ldb = max(ldb, B.shape[2]); ldc = max(ldc, n)
     args = (int(transA), int(transB), m, n, k, _ptr(A), lda, psA, _ptr(B), ldb, psB,
             _ptr(out), ldc, psC, _stream())
@@ -273,6 +293,7 @@ def gemm_ozaki_dd(A, B, slices, beta=20, kblk=256, out=None, ws=None):
     if out is None:
         out = torch.empty((2, m, n), dtype=torch.float64, device=A.device)
     psC, ldc = _planes(out, DD, 2, "out")
+    _expect(out, (2, m, n), "out")
     if ws is None:
         ws = workspace(OP_OZAKI, DD, m, n, k, slices)
     _check(lib().mpx_gemm_ozaki_dd(m, n, k, _ptr(A), max(lda, k), psA, _ptr(B), max(ldb, n), psB,
@@ -288,14 +309,16 @@ def cgemm_3m(p, Are, Aim, Bre, Bim, out=None, ws=None):
     psB, ldb = _planes(Bre, p, 2, "Bre")
     for t, ref, name in ((Aim, Are, "Aim"), (Bim, Bre, "Bim")):
         _planes(t, p, 2, name)
-        if t.shape != ref.shape or t.stride() != ref.stride():
-            raise ValueError(f"{name} must match the real part's shape and strides")
+        _same_layout(t, ref, name, "the real part")
     m, n, k = _gemm_shapes(Are, Bre, False, False)
     if out is None:
         out = (torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=Are.device),
                torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=Are.device))
     Cre, Cim = out
     psC, ldc = _planes(Cre, p, 2, "Cre")
+    _planes(Cim, p, 2, "Cim")
+    _expect(Cre, (ncomp(p), m, n), "Cre")
+    _same_layout(Cim, Cre, "Cim", "Cre")
     if ws is None:
         ws = workspace(OP_CGEMM, p, m, n, k)
     _check(lib().mpx_cgemm_3m(p, m, n, k, _ptr(Are), _ptr(Aim), max(lda, k), psA, _ptr(Bre),
@@ -313,6 +336,7 @@ def gemm_strassen(p, A, B, cutoff, out=None, ws=None):
     if out is None:
         out = torch.empty((ncomp(p), m, n), dtype=dtype_of(p), device=A.device)
     psC, ldc = _planes(out, p, 2, "out")
+    _expect(out, (ncomp(p), m, n), "out")
     if ws is None:
         ws = workspace(OP_STRASSEN, p, m, n, k, cutoff)
     _check(lib().mpx_gemm_strassen(p, m, n, k, _ptr(A), max(lda, k), psA, _ptr(B), max(ldb, n), psB,
@@ -368,11 +392,13 @@ class GemmBatchPlan:
         return a[:-1], b[:-1], c[:-1], (int(a[-1]), int(b[-1]), int(c[-1]))
 
     def _args(self, A, B, Cm):
-        for t, name in ((A, "A"), (B, "B"), (Cm, "C")):
+        totals = self.offsets()[3]
+        for t, name, tot in ((A, "A", totals[0]), (B, "B", totals[1]), (Cm, "C", totals[2])):
             if t.dim() != 2 or t.shape[0] != ncomp(self.p) or t.dtype != dtype_of(self.p) or not t.is_cuda:
                 raise ValueError(f"{name}: expected a (K, total) GPU tensor of the plan's precision")
             if t.shape[1] > 1 and t.stride(1) != 1:
                 raise ValueError(f"{name}: planes must be contiguous")
+            _expect(t, (ncomp(self.p), tot), name)
         return (_ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(Cm), Cm.stride(0))
 
     def run(self, A, B, Cm):
@@ -446,6 +472,7 @@ def polyval(p, coef, x, out=None, method="horner"):
     if out is None:
         out = torch.empty((K, batch), dtype=torch.float64, device=coef.device)
     psy, _ = _planes(out, p, 1, "out")
+    _expect(out, (K, batch), "out")
     fn = {"horner": lib().mpx_polyval, "estrin": lib().mpx_polyval_estrin}[method]
     _check(fn(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(x), psx, _ptr(out), psy,
               _stream()), f"polyval ({method})")
@@ -463,8 +490,8 @@ def polyval_cplx(p, coef, xre, xim, out=None, method="horner"):
         raise ValueError("coef must be (K, batch, deg+1)")
     coef = coef.contiguous()
     psx, _ = _planes(xre, p, 1, "xre")
-    if _planes(xim, p, 1, "xim")[0] != psx or xim.shape != xre.shape:
-        raise ValueError("xim must match xre's shape and plane stride")
+    _planes(xim, p, 1, "xim")
+    _same_layout(xim, xre, "xim", "xre")
     batch, d1 = coef.shape[1], coef.shape[2]
     if xre.shape[1] != batch:
         raise ValueError("one point per polynomial")
@@ -473,8 +500,9 @@ def polyval_cplx(p, coef, xre, xim, out=None, method="horner"):
                torch.empty((K, batch), dtype=torch.float64, device=coef.device))
     yre, yim = out
     psy, _ = _planes(yre, p, 1, "yre")
-    if _planes(yim, p, 1, "yim")[0] != psy:
-        raise ValueError("yim must match yre's plane stride")
+    _planes(yim, p, 1, "yim")
+    _expect(yre, (K, batch), "yre")
+    _same_layout(yim, yre, "yim", "yre")
     _check(lib().mpx_polyval_cplx(p, batch, d1 - 1, _ptr(coef), coef.stride(0), _ptr(xre), _ptr(xim),
                                   psx, _ptr(yre), _ptr(yim), psy, {"horner": 0, "estrin": 1}[method],
                                   _stream()), f"polyval_cplx ({method})")
@@ -485,10 +513,14 @@ def polyval_backward(p, coef, x, gy, want_coef=True, want_x=True):
     """(dL/dcoef, dL/dx) for L = sum_b gy_b p_b(x_b); entries None when not wanted."""
     p = prec_of(p)
     K = ncomp(p)
+    if coef.dim() != 3 or coef.shape[0] != K:
+        raise ValueError("coef must be (K, batch, deg+1)")
     coef = coef.contiguous()
     psx, _ = _planes(x, p, 1, "x")
     psg, _ = _planes(gy, p, 1, "gy")
     batch, d1 = coef.shape[1], coef.shape[2]
+    _expect(x, (K, batch), "x")
+    _expect(gy, (K, batch), "gy")
     gc = torch.empty_like(coef) if want_coef else None
     gx = torch.empty((K, batch), dtype=torch.float64, device=coef.device) if want_x else None
     _check(lib().mpx_polyval_backward(
@@ -545,6 +577,9 @@ class RootsPlan:
         self._args(coef_re, coef_im, roots_re, roots_im)
         if status is None:
             status = torch.zeros(self.degrees.size, dtype=torch.int32, device=coef_re.device)
+        if status.dtype != torch.int32 or not status.is_cuda or status.dim() != 1 or \
+                status.shape[0] != self.degrees.size or (status.numel() > 1 and status.stride(0) != 1):
+            raise ValueError(f"status: expected a contiguous int32 GPU tensor of {self.degrees.size} values")
         _check(lib().mpx_polyroots(self._h, _ptr(coef_re), _ptr(coef_im), coef_re.stride(0),
                                    _ptr(roots_re), _ptr(roots_im), roots_re.stride(0),
                                    _ptr(status), _stream()), "mpx_polyroots")

@@ -100,8 +100,11 @@ def test_batched_argument_errors():
         mpx.GemmBatchPlan("qd", [2, -1], [2, 2], [2, 2])
     plan = mpx.GemmBatchPlan("dd", [4], [4], [4])
     small = torch.zeros((2, 8), dtype=torch.float64, device="cuda")
-    with pytest.raises(mpx.MpxError):
-        plan.run(small, small, small)        # C needs 16 elements per plane
+    with pytest.raises(ValueError):
+        plan.run(small, small, small)        # the binding: 16 elements per plane
+    # the library itself: plane stride 8 < 16, rejected before any launch
+    p8 = mpx._ptr(small)
+    assert mpx.lib().mpx_gemm_batched(plan._h, p8, 8, p8, 8, p8, 8, None) == -1
     with pytest.raises(mpx.MpxError):
         plan.set_variant(99)
 

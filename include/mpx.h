@@ -35,9 +35,14 @@
  * finite and normal (Section 2); NaN / Inf / subnormal handling is
  * unspecified.  Outputs may alias inputs only for mpx_add / mpx_mul (z may
  * equal x or y) and mpx_axpy (y in place).  The dot, GEMV and GEMM family
- * (plain, batched, Strassen, 3M, Ozaki) reject with MPX_EINVAL an output
- * whose memory range (all K planes) overlaps an input's, or a workspace
- * overlapping any operand.
+ * (plain, batched, Strassen, 3M, Ozaki), the polynomial evaluations (Horner,
+ * Estrin, complex points, backward) and the root solver reject with
+ * MPX_EINVAL an output whose memory range overlaps an input's or another
+ * output's, or a workspace overlapping any operand (the root solver: roots
+ * overlapping the coefficients or each other, a status array overlapping any
+ * of them).  A range runs from a buffer's first element in plane 0 to its
+ * last element in plane K - 1, so buffers whose planes interleave inside one
+ * allocation count as overlapping.
  *
  * Determinism: every call is bitwise reproducible for the same arguments.
  * Elementwise ops, AXPY, GEMM (plain, batched, Strassen, 3M), Horner,

@@ -38,9 +38,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 namespace mpx {
@@ -756,6 +758,21 @@ using namespace mpx;
 
 // ---------------------------------------------------------------- C ABI ----
 
+// Byte extent of K planes of n binary64 values at plane stride ps.
+static uint64_t vec_bytes(int K, int64_t n, int64_t ps) {
+    return planes_bytes(K, 1, n, n, ps, sizeof(double));
+}
+
+// Does the output range [out, out + nb) overlap the coefficient planes or any
+// of the point / weight vectors (batch values per plane at stride psv)?
+static bool poly_out_overlaps(int K, const void* out, uint64_t nb, int64_t batch, int64_t deg,
+                              const void* coef, int64_t psc, const void* v0, const void* v1,
+                              const void* v2, int64_t psv) {
+    const uint64_t cb = vec_bytes(K, batch * (deg + 1), psc), vb = vec_bytes(K, batch, psv);
+    return overlaps(out, nb, coef, cb) || overlaps(out, nb, v0, vb) || overlaps(out, nb, v1, vb) ||
+           overlaps(out, nb, v2, vb);
+}
+
 static int polyval_check(int prec, int64_t batch, int64_t deg, const void* coef, int64_t psc,
                          const void* x, int64_t psx) {
     if (prec != MPX_DD && prec != MPX_TD && prec != MPX_QD) return MPX_EPREC;
@@ -774,6 +791,9 @@ extern "C" int mpx_polyval(int prec, int64_t batch, int64_t deg, const void* coe
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (y == nullptr || psy < batch) return MPX_EINVAL;
+    if (poly_out_overlaps(prec_k_ar(prec), y, vec_bytes(prec_k_ar(prec), batch, psy), batch, deg,
+                          coef, psc, x, nullptr, nullptr, psx))
+        return MPX_EINVAL;
     const unsigned blocks = (unsigned)ceil_div(batch, 64);
     hipStream_t s = as_stream(stream);
 #define MPX_PV(K_, AR_)                                                                     \
@@ -846,6 +866,14 @@ extern "C" int mpx_polyval_cplx(int prec, int64_t batch, int64_t deg, const void
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (xim == nullptr || yre == nullptr || yim == nullptr || psy < batch) return MPX_EINVAL;
+    {
+        const int K = prec_k_ar(prec);
+        const uint64_t yb = vec_bytes(K, batch, psy);
+        if (poly_out_overlaps(K, yre, yb, batch, deg, coef, psc, xre, xim, nullptr, psx) ||
+            poly_out_overlaps(K, yim, yb, batch, deg, coef, psc, xre, xim, nullptr, psx) ||
+            overlaps(yre, yb, yim, yb))
+            return MPX_EINVAL;
+    }
     hipStream_t s = as_stream(stream);
     if (method == 1) {
         if (deg >= 1024) return MPX_ENOTSUP;  // 16 coefficients per lane at most
@@ -882,6 +910,9 @@ extern "C" int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const vo
     if (st) return st;
     if (batch == 0) return MPX_OK;
     if (y == nullptr || psy < batch) return MPX_EINVAL;
+    if (poly_out_overlaps(prec, y, vec_bytes(prec, batch, psy), batch, deg, coef, psc, x, nullptr,
+                          nullptr, psx))
+        return MPX_EINVAL;
     // degree >= 2048 would need 64 coefficients per lane; the QD build of that
     // shape exceeds the register file and its results did not match the
     // sequential definition, so it is not offered
@@ -905,6 +936,18 @@ extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const 
     if (gcoef && !prod_fits(batch, deg + 1, psgc)) return MPX_EINVAL;
     if (gx && psgx < batch) return MPX_EINVAL;
     if (!gcoef && !gx) return MPX_OK;
+    {
+        // x and gy are both batch values per plane, at their own strides
+        const int K = prec;
+        const uint64_t gcb = gcoef ? vec_bytes(K, batch * (deg + 1), psgc) : 0;
+        const uint64_t gxb = gx ? vec_bytes(K, batch, psgx) : 0;
+        const uint64_t gyb = vec_bytes(K, batch, psg);
+        for (const auto& o : {std::make_pair((const void*)gcoef, gcb), std::make_pair((const void*)gx, gxb)})
+            if (poly_out_overlaps(K, o.first, o.second, batch, deg, coef, psc, x, nullptr, nullptr, psx) ||
+                overlaps(o.first, o.second, gy, gyb))
+                return MPX_EINVAL;
+        if (overlaps(gcoef, gcb, gx, gxb)) return MPX_EINVAL;
+    }
     const unsigned blocks = (unsigned)ceil_div(batch, 64);
     hipStream_t s = as_stream(stream);
 #define MPX_PB(KK)                                                                             \
@@ -1088,6 +1131,12 @@ static int roots_check(mpx_plan p, const void* cre, const void* cim, int64_t psc
     if (p->batch == 0) return MPX_OK;
     if (!cre || !cim || !rre || !rim) return MPX_EINVAL;
     if (psc < p->total_coef || psr < p->total_roots) return MPX_EINVAL;
+    // the roots are updated in place; they must not overlap the coefficients
+    // or each other
+    const uint64_t cb = vec_bytes(p->K, p->total_coef, psc), rb = vec_bytes(p->K, p->total_roots, psr);
+    if (overlaps(rre, rb, cre, cb) || overlaps(rre, rb, cim, cb) || overlaps(rim, rb, cre, cb) ||
+        overlaps(rim, rb, cim, cb) || overlaps(rre, rb, rim, rb))
+        return MPX_EINVAL;
     return MPX_OK;
 }
 
@@ -1097,6 +1146,13 @@ extern "C" int mpx_polyroots(mpx_plan p, const void* coef_re, const void* coef_i
     int st = roots_check(p, coef_re, coef_im, psc, roots_re, roots_im, psr);
     if (st) return st;
     if (p->batch == 0) return MPX_OK;
+    if (status) {
+        const uint64_t sb = (uint64_t)p->batch * sizeof(int32_t);
+        const uint64_t cb = vec_bytes(p->K, p->total_coef, psc), rb = vec_bytes(p->K, p->total_roots, psr);
+        if (overlaps(status, sb, coef_re, cb) || overlaps(status, sb, coef_im, cb) ||
+            overlaps(status, sb, roots_re, rb) || overlaps(status, sb, roots_im, rb))
+            return MPX_EINVAL;
+    }
     hipStream_t s = as_stream(stream);
     if (!(p->flags & MPX_DK_GRAPH) || s == nullptr)
         return launch_dk(p, p->variant, coef_re, coef_im, psc, roots_re, roots_im, psr, status, s);

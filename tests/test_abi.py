@@ -169,3 +169,31 @@ def test_overlapping_outputs_rejected():
                           1 << 20, None) == -1                                              # Cre == Are
     assert L.mpx_gemv(4, 0, 4, 4, A, 4, 16, B, 4, inside_A, 4, None, 0, None) == -1         # y in A
     assert L.mpx_dot(4, 8, A, 8, B, 8, C.c_void_p(base + 8 * 8), None, 0, None) == -1      # result in x
+
+
+def test_polynomial_outputs_overlapping_inputs_rejected():
+    """Horner / Estrin / complex-point evaluation and the backward pass reject
+    outputs that overlap the coefficients, the points, the weights or each
+    other (checked on the pointer ranges of all K planes, before any launch)."""
+    L = mpx.lib()
+    base = 1 << 40
+    coef = C.c_void_p(base)                              # QD, 8 polynomials of degree 3: 32 per plane
+    x = C.c_void_p(base + (1 << 20))
+    y = C.c_void_p(base + (2 << 20))
+    in_coef = C.c_void_p(base + 2 * 32 * 8)              # plane 2 of the coefficients
+    in_x = C.c_void_p(base + (1 << 20) + 3 * 8 * 8)      # plane 3 of x
+    for fn in (L.mpx_polyval, L.mpx_polyval_estrin):
+        assert fn(4, 8, 3, coef, 32, x, 8, in_coef, 8, None) == -1
+        assert fn(4, 8, 3, coef, 32, x, 8, in_x, 8, None) == -1
+        assert fn(4, 8, 3, coef, 32, x, 8, x, 8, None) == -1
+    xi, yi = C.c_void_p(base + (3 << 20)), C.c_void_p(base + (4 << 20))
+    assert L.mpx_polyval_cplx(4, 8, 3, coef, 32, x, xi, 8, y, y, 8, 0, None) == -1      # yre == yim
+    assert L.mpx_polyval_cplx(4, 8, 3, coef, 32, x, xi, 8, y, xi, 8, 0, None) == -1     # yim == xim
+    assert L.mpx_polyval_cplx(4, 8, 3, coef, 32, x, xi, 8, in_coef, yi, 8, 1, None) == -1
+    gy = C.c_void_p(base + (5 << 20))
+    gc = C.c_void_p(base + (6 << 20))
+    assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, None, 0, gy, 8, None) == -1   # gx == gy
+    assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, in_coef, 32, None, 0, None) == -1
+    assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, gc, 32, in_x, 8, None) == -1
+    assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, gc, 32,
+                                  C.c_void_p(base + (6 << 20) + 8), 8, None) == -1           # gx in gcoef

@@ -72,3 +72,28 @@ def test_plan_operands_checked():
         rp.run(cre, cim, zr, zi, status=torch.zeros(1, dtype=torch.int32, device="cuda"))
     with pytest.raises(ValueError):
         rp.run(cre, cim, zr, zi, status=torch.zeros(2, dtype=torch.int64, device="cuda"))
+
+
+def test_root_solver_rejects_overlapping_buffers():
+    """The library (called directly): roots overlapping the coefficients or
+    each other, and a status array overlapping any of them, are argument
+    errors returned before any launch (ranges cover all K planes)."""
+    import ctypes as C
+    L = mpx.lib()
+    rp = mpx.RootsPlan("dd", [3, 5], iters=1, init=True, graph=False)
+    cre, cim = _z(2, rp.total_coef), _z(2, rp.total_coef)
+    zr, zi = _z(2, rp.total_roots), _z(2, rp.total_roots)
+    pc, pr = cre.stride(0), zr.stride(0)
+    ptr = lambda t, off=0: C.c_void_p(t.data_ptr() + 8 * off)
+    h = rp._h
+    assert L.mpx_polyroots(h, ptr(cre), ptr(cim), pc, ptr(cre), ptr(zi), pr, None, None) == -1
+    assert L.mpx_polyroots(h, ptr(cre), ptr(cim), pc, ptr(zr), ptr(cim, 3), pr, None, None) == -1
+    assert L.mpx_polyroots(h, ptr(cre), ptr(cim), pc, ptr(zr), ptr(zr, 2), pr, None, None) == -1
+    assert L.mpx_polyroots(h, ptr(cre), ptr(cim), pc, ptr(zr), ptr(zi), pr, ptr(zi, 1), None) == -1
+    # the same buffers without overlap are accepted (and solved)
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    cre[0, 0] = -1.0; cre[0, 3] = 1.0                # x^3 - 1
+    cre[0, 4] = -1.0; cre[0, 9] = 1.0                # x^5 - 1
+    mpx.RootsPlan("dd", [3, 5], iters=0, init=True, graph=False).run(cre, cim, zr, zi)
+    assert L.mpx_polyroots(h, ptr(cre), ptr(cim), pc, ptr(zr), ptr(zi), pr, ptr(st), None) == 0
+    torch.cuda.synchronize()

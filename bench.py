@@ -145,7 +145,7 @@ def gemm_row(mpx, torch, T, p, n, reps):
             "variant": mpx.gemm_variants(p)[v]}
 
 
-def cpu_baseline(p, n, target_s=12.0):
+def cpu_baseline(p, n, target_s=20.0):
     """The CPU oracle (sequential triple loop per entry) on a row sample of
     the same n x n x n product, OpenMP over rows, timed on the host."""
     import oracle

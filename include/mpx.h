@@ -358,8 +358,9 @@ int mpx_plan_destroy(mpx_plan plan);
  * results do not depend on the variant.  A new plan uses the packed schedule
  * with 8 resident waves per CU.  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants
- * (a variant's time is its faster round), keeps the fastest in the plan
- * and returns its index (or a negative status).  Synchronises; allocates. */
+ * (a variant's time is its faster round), switches the plan to the fastest
+ * only when it beats the plan's current variant by at least 3 %, and returns
+ * the index kept (or a negative status).  Synchronises; allocates. */
 int mpx_polyroots_variant_count(void);
 int mpx_polyroots_set_variant(mpx_plan plan, int variant);
 int mpx_polyroots_autotune(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,

@@ -89,6 +89,24 @@ def test_dk_aberth_start_close_to_oracle(p, K):
     assert np.all(gr[1:] == 0) and np.all(gi[1:] == 0)
 
 
+def test_dk_autotune_leaves_roots_and_results_unchanged():
+    """The autotuner probes every variant on a private copy of the start
+    roots, keeps a valid variant in the plan (the default unless another is
+    clearly faster), and the tuned plan gives the oracle's bits."""
+    K = 4
+    deg, cre, cim = _dk_inputs(K, RAGGED * 8, 60)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, _ = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=5, init=False)
+    plan = mpx.RootsPlan("qd", deg, iters=5, init=False, graph=False)
+    gc_r, gc_i = to_gpu(cre), to_gpu(cim)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    v, ms = plan.autotune(gc_r, gc_i, zr, zi, iters_probe=2)
+    assert 0 <= v < mpx.polyroots_variant_count() and ms > 0
+    assert bits_equal(to_np(zr), z0r) and bits_equal(to_np(zi), z0i)   # start roots untouched
+    plan.run(gc_r, gc_i, zr, zi)
+    assert bits_equal(to_np(zr), wr) and bits_equal(to_np(zi), wi), v
+
+
 def test_dk_graph_replay_matches_eager():
     K = 4
     deg, cre, cim = _dk_inputs(K, [16, 31, 48, 3, 9], 40)

@@ -65,8 +65,9 @@ def parse():
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
     ap.add_argument("--only", default=None,
                     choices=["gemm", "gemv", "vector", "cgemm", "polyeval", "nobf", "strassen", "batched",
-                             "durand_kerner", "autograd", "ozaki"],
-                    help="measure one row only (skips the headline and the CPU baseline)")
+                             "durand_kerner", "autograd", "ozaki", "vector_sweep"],
+                    help="measure one row only (skips the headline and the CPU baseline); "
+                         "vector_sweep (n = 2^16 .. 2^26) runs only when named here")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--peak-probe", action="store_true",
                     help="measure the FP64 / FP32 VALU issue rates the rooflines use, print them, exit")
@@ -232,6 +233,55 @@ def vector_rows(mpx, torch, T):
                     row[str(n)][f"{name}_graph_calls_per_s"] = 1.0 / (tg * 1e-3)
                     del g
         out[p] = row
+    return out
+
+
+def vector_sweep_rows(mpx, torch, T):
+    """Bandwidth sweep (an extension of the n = 4096 / 2^24 rows): elementwise
+    add, AXPY and dot for n = 2^16 .. 2^26, DD / TD / QD, GB/s against the
+    8 TB/s HBM peak.  One QD pair of 2^26 elements (a seeded block of 1000003
+    values repeated) serves every row: smaller n and K use its leading
+    components and elements (plane stride 2^26)."""
+    from paper_2603_14926_amd import synth
+    nmax, period = 1 << 26, 1_000_003
+
+    def tiled(seed):
+        # the seeded block repeated along the planes (generating 2^26 QD values
+        # on the host takes minutes; streaming bandwidth does not see values)
+        base = gpu_mp(torch, 4, period, seed)
+        t = torch.empty((4, nmax), dtype=torch.float64, device="cuda")
+        q, rem = divmod(nmax, period)
+        t[:, :q * period].view(4, q, period).copy_(base[:, None, :].expand(4, q, period))
+        t[:, q * period:].copy_(base[:, :rem])
+        return t
+
+    x4, y4 = tiled(synth.seed_for(0, 11)), tiled(synth.seed_for(0, 12))
+    z4 = torch.empty_like(x4)
+    out = {}
+    for p in ("qd", "td", "dd"):
+        K = mpx.ncomp(p)
+        alpha = [0.75] + [0.0] * (K - 1)
+        r = torch.empty(K, dtype=torch.float64, device="cuda")
+        for lg in range(16, 27, 2):
+            n = 1 << lg
+            x, y, z = x4[:K, :n], y4[:K, :n], z4[:K, :n]
+            ws = mpx.workspace(mpx.OP_DOT, p, n)
+            reps = 100 if n <= (1 << 20) else 10
+            # best of three batches: one stall inside a batch of short calls
+            # would otherwise dominate its mean
+            best = lambda fn: min(T(fn, reps=reps) for _ in range(3))
+            t_add = best(lambda: mpx.add(p, x, y, out=z))
+            t_axpy = best(lambda: mpx.axpy(p, alpha, x, z))
+            t_dot = best(lambda: mpx.dot(p, x, y, out=r, ws=ws))
+            b3, b2 = 3 * K * 8.0 * n, 2 * K * 8.0 * n
+            out[f"{p}_2^{lg}"] = {
+                "add_us": t_add * 1e3, "add_GB_s": b3 / (t_add * 1e-3) / 1e9,
+                "axpy_us": t_axpy * 1e3, "axpy_GB_s": b3 / (t_axpy * 1e-3) / 1e9,
+                "dot_us": t_dot * 1e3, "dot_GB_s": b2 / (t_dot * 1e-3) / 1e9,
+                "frac_hbm": {"add": b3 / (t_add * 1e-3) / PEAK_HBM, "axpy": b3 / (t_axpy * 1e-3) / PEAK_HBM,
+                             "dot": b2 / (t_dot * 1e-3) / PEAK_HBM},
+            }
+    del x4, y4, z4
     return out
 
 
@@ -630,6 +680,7 @@ def main():
         fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd")},
               "gemv": lambda: gemv_rows(mpx, torch, T),
               "vector": lambda: vector_rows(mpx, torch, T),
+              "vector_sweep": lambda: vector_sweep_rows(mpx, torch, T),
               "cgemm": lambda: cgemm_rows(mpx, torch, T),
               "polyeval": lambda: polyeval_rows(mpx, torch, T),
               "nobf": lambda: nobf_rows(mpx, torch, T),

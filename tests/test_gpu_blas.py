@@ -199,18 +199,20 @@ def test_gemm_2048_sampled_bit_exact(p, K, dt, dist):
     assert np.all(np.isfinite(got))
 
 
-def test_gemm_paper_matrices_digits():
-    """The real test matrices of Section 3.1 at n = 512 reach the paper's
-    digit ranges (DD >= 29.0, TD >= 45.5, QD >= 61.7)."""
+@pytest.mark.parametrize("n", [512, 1024, 2048, 2049])
+def test_gemm_paper_matrices_digits(n):
+    """The real test matrices of Section 3.1 at the paper's sizes reach its
+    digit ranges (DD >= 29.0, TD >= 45.5, QD >= 61.7) against the closed
+    form, on sampled entries (corners, interior, the last row and column)."""
     import math
-    n = 512
     s15 = synth.sqrt_fraction(15, bits=400)
     need_by_k = paper_values.gemm_digits("real")     # tests/golden/gemm_digits.txt
+    entries = ((0, 0), (100, 7), (n - 1, n - 1), (n // 2 - 1, 400), (0, n - 1), (n - 1, 0))
     for p, K in (("dd", 2), ("td", 3), ("qd", 4)):
         need = need_by_k[K]
         A, B = synth.paper_real_gemm(K, n)
         got = to_np(mpx.gemm(p, to_gpu(A), to_gpu(B)))
-        for (i, j) in ((0, 0), (100, 7), (511, 511), (255, 400)):
+        for (i, j) in entries:
             ex = s15 * synth.paper_real_gemm_exact(n, i, j)
             rel = abs(exact.value(got[:, i, j]) - ex) / ex
             digits = -math.log10(float(rel)) if rel else 99.0

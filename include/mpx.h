@@ -341,10 +341,12 @@ int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef,
  * 4-wave jobs) and working buffers (monic coefficients, second iterate) and
  * frees them in mpx_plan_destroy.  The constructor returns MPX_EINVAL for a
  * degree below 1 or unknown flags, MPX_ENOTSUP when the batch holds more than
- * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when allocation fails.  With MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots
- * captures its launches into a HIP graph on first use and replays it while
- * buffers and stream stay the same.  One persistent launch processes the
- * whole batch.  Calls on one plan must not overlap. */
+ * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when allocation fails.  With
+ * MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots captures its launches
+ * into a HIP graph on first use and replays it while buffers and stream stay
+ * the same; on a stream the caller is already capturing it launches
+ * directly, so the caller's graph records the launches.  One persistent
+ * launch processes the whole batch.  Calls on one plan must not overlap. */
 typedef struct mpx_plan_s *mpx_plan;
 enum { MPX_DK_INIT = 1, MPX_DK_GRAPH = 2 };
 int mpx_polyroots_plan(mpx_plan *out, int prec, int64_t batch, const int32_t *degree_host,

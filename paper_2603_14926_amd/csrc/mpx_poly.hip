@@ -1154,7 +1154,11 @@ extern "C" int mpx_polyroots(mpx_plan p, const void* coef_re, const void* coef_i
             return MPX_EINVAL;
     }
     hipStream_t s = as_stream(stream);
-    if (!(p->flags & MPX_DK_GRAPH) || s == nullptr)
+    // Inside a capture the caller already owns (its graph records these
+    // launches), and without the graph flag or a stream, launch directly.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (s != nullptr && hipStreamIsCapturing(s, &cap) != hipSuccess) return MPX_EDEVICE;
+    if (!(p->flags & MPX_DK_GRAPH) || s == nullptr || cap != hipStreamCaptureStatusNone)
         return launch_dk(p, p->variant, coef_re, coef_im, psc, roots_re, roots_im, psr, status, s);
     // Graph path: capture the launch sequence once per (buffers, stream, variant), replay after.
     const void* key[6] = {coef_re, coef_im, roots_re, roots_im, status, nullptr};

@@ -129,6 +129,33 @@ def test_dk_graph_replay_matches_eager():
         assert int(to_np(st).sum()) == 0
 
 
+def test_dk_plan_with_graph_flag_inside_an_outer_capture():
+    """A plan created with the graph flag, called while the caller captures
+    the stream, launches directly into the caller's graph; replays of that
+    graph reproduce the oracle's iterates."""
+    K = 4
+    deg, cre, cim = _dk_inputs(K, [16, 31, 48, 3, 9], 41)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, _ = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=3, init=False)
+    plan = mpx.RootsPlan("qd", deg, iters=3, init=False, graph=True)
+    gc_r, gc_i = to_gpu(cre), to_gpu(cim)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    st = torch.zeros(deg.size, dtype=torch.int32, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        plan.run(gc_r, gc_i, zr, zi, status=st)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        zr.copy_(to_gpu(z0r)); zi.copy_(to_gpu(z0i))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+        assert bits_equal(to_np(zr), wr) and bits_equal(to_np(zi), wi), rep
+
+
 def test_dk_known_roots_and_status():
     K = 4
     deg, cre, cim, known = synth.dk_batch(K, 6, 16, 40, seed=50, n_known=4, known_degree=16)

@@ -204,7 +204,9 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
  * mpx_gemm_batched_autotune times each tiling on the caller's buffers (C is
  * overwritten) in two rounds over all tilings (a tiling's time is its faster
  * round), keeps the fastest in the plan and returns its index (it
- * synchronises the stream).  Errors as for mpx_gemm. */
+ * synchronises the stream).  Errors as for mpx_gemm; the constructor also
+ * returns MPX_ENOTSUP when a tiling's work list would pass 2^30 items and
+ * MPX_EDEVICE when a host or device allocation fails. */
 typedef struct mpx_gemm_plan_s *mpx_gemm_plan;
 int mpx_gemm_batched_plan(mpx_gemm_plan *out, int prec, int64_t count, const int64_t *m_host,
                           const int64_t *n_host, const int64_t *k_host);
@@ -341,7 +343,8 @@ int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef,
  * 4-wave jobs) and working buffers (monic coefficients, second iterate) and
  * frees them in mpx_plan_destroy.  The constructor returns MPX_EINVAL for a
  * degree below 1 or unknown flags, MPX_ENOTSUP when the batch holds more than
- * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when allocation fails.  With
+ * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when a host or device allocation
+ * fails.  With
  * MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots captures its launches
  * into a HIP graph on first use and replays it while buffers and stream stay
  * the same; on a stream the caller is already capturing it launches

@@ -35,6 +35,7 @@
 #include <mutex>
 #include <new>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <vector>
 
@@ -616,25 +617,24 @@ struct mpx_gemm_plan_s {
     int* counter = nullptr;
 };
 
-extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count,
-                                     const int64_t* m, const int64_t* n, const int64_t* k) {
+static int gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count, const int64_t* m,
+                             const int64_t* n, const int64_t* k) {
     using namespace mpx;
     if (out == nullptr) return MPX_EINVAL;
     *out = nullptr;
     if (!prec_k(prec)) return MPX_EPREC;
     if (count < 0 || count > INT32_MAX || (count > 0 && (!m || !n || !k))) return MPX_EINVAL;
-    auto* p = new (std::nothrow) mpx_gemm_plan_s();
-    if (!p) return MPX_EINVAL;
+    std::unique_ptr<mpx_gemm_plan_s> holder(new (std::nothrow) mpx_gemm_plan_s());
+    if (!holder) return MPX_EDEVICE;
+    mpx_gemm_plan_s* p = holder.get();
     p->prec = prec;
     p->count = (int)count;
     p->vars = gb_variants(prec);
     std::vector<GbProb> probs(count);
     for (int64_t i = 0; i < count; ++i) {
         if (m[i] < 0 || n[i] < 0 || k[i] < 0 || m[i] > (1 << 20) || n[i] > (1 << 20) ||
-            k[i] > (1 << 20)) {
-            delete p;
+            k[i] > (1 << 20))
             return MPX_EINVAL;
-        }
         probs[i] = GbProb{(int)m[i], (int)n[i], (int)k[i], p->totA, p->totB, p->totC};
         p->totA += m[i] * k[i];
         p->totB += k[i] * n[i];
@@ -647,10 +647,7 @@ extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count
         for (int64_t i = 0; i < count; ++i)
             nit += (v.mixed ? 4 * ceil_div(probs[i].m, 8) * ceil_div(probs[i].n, 8)
                             : ceil_div(probs[i].m, v.bm) * ceil_div(probs[i].n, v.bn));
-        if (nit > INT32_MAX / 2) {  // the work counter is an int
-            delete p;
-            return MPX_ENOTSUP;
-        }
+        if (nit > INT32_MAX / 2) return MPX_ENOTSUP;  // the work counter is an int
     }
     auto by_k = [&](const GbItem& a, const GbItem& b) { return probs[a.p].k > probs[b.p].k; };
     for (const auto& v : p->vars) {
@@ -699,7 +696,7 @@ extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count
     const size_t sz_i = std::max<size_t>(all.size(), 1) * sizeof(GbItem);
     const size_t off_i = (sz_p + 255) & ~size_t(255), off_c = (off_i + sz_i + 255) & ~size_t(255);
     if (hipMalloc(&p->dev, off_c + 256) != hipSuccess) {
-        delete p;
+        p->dev = nullptr;
         return MPX_EDEVICE;
     }
     p->probs = (GbProb*)p->dev;
@@ -710,15 +707,26 @@ extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count
         (!all.empty() && hipMemcpy(p->items, all.data(), all.size() * sizeof(GbItem),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
         (void)hipFree(p->dev);
-        delete p;
+        p->dev = nullptr;
         return MPX_EDEVICE;
     }
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         p->cus = prop.multiProcessorCount;
-    *out = p;
+    *out = holder.release();
     return MPX_OK;
+}
+
+// Host allocation failures (the schedule's vectors) end as MPX_EDEVICE: no
+// exception crosses the C boundary.
+extern "C" int mpx_gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count,
+                                     const int64_t* m, const int64_t* n, const int64_t* k) {
+    try {
+        return gemm_batched_plan(out, prec, count, m, n, k);
+    } catch (const std::bad_alloc&) {
+        return MPX_EDEVICE;
+    }
 }
 
 extern "C" int mpx_gemm_plan_destroy(mpx_gemm_plan p) {

@@ -963,8 +963,8 @@ extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const 
     return launch_status();
 }
 
-extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
-                                  const int32_t* degree_host, int iters, uint32_t flags) {
+static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t* degree_host,
+                          int iters, uint32_t flags) {
     if (out == nullptr) return MPX_EINVAL;
     *out = nullptr;
     if (!prec_k_ar(prec) || base_prec(prec) == MPX_FF) return MPX_EPREC;
@@ -1063,7 +1063,7 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
     }
 
     auto* p = new (std::nothrow) mpx_plan_s();
-    if (!p) return MPX_EINVAL;
+    if (!p) return MPX_EDEVICE;
     p->prec = prec;
     p->K = prec_k_ar(prec);
     p->batch = (int)batch;
@@ -1114,6 +1114,17 @@ extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
                      d_cnt, psm, psz, d_jo, d_it, (int)(job_off.size() - 1)};
     *out = p;
     return MPX_OK;
+}
+
+// Host allocation failures (the schedule's vectors, all made before the plan
+// itself) end as MPX_EDEVICE: no exception crosses the C boundary.
+extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
+                                  const int32_t* degree_host, int iters, uint32_t flags) {
+    try {
+        return polyroots_plan(out, prec, batch, degree_host, iters, flags);
+    } catch (const std::bad_alloc&) {
+        return MPX_EDEVICE;
+    }
 }
 
 extern "C" int mpx_plan_destroy(mpx_plan p) {

@@ -27,19 +27,32 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout.strip() == ""            # no JSON line for an unmeasured N
 
 
+def _sources_hash(root, files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def test_traffic_only_from_counters_on_current_sources(tmp_path):
     bench = _bench()
     rec = json.load(open(os.path.join(ROOT, "profiles", "qd_gemm_2048_counters.json")))
     assert "paper_2603_14926_amd/csrc/mpx_gemm.hip" in rec["sources"]
-    assert bench.measured_traffic("qd_gemm_2048") == rec["traffic_bytes"]
+    # the tree itself: the recorded figure exactly when the sources match
+    fresh = _sources_hash(ROOT, rec["sources"]) == rec["source_sha256_16"]
+    assert bench.measured_traffic("qd_gemm_2048") == (rec["traffic_bytes"] if fresh else None)
     assert bench.measured_traffic("no_such_workload") is None
-    # a copy of the tree whose GEMM source differs by one byte: no traffic
+    # a copy whose record matches its sources, then one byte changed: no traffic
     os.makedirs(tmp_path / "profiles")
-    shutil.copy(os.path.join(ROOT, "profiles", "qd_gemm_2048_counters.json"), tmp_path / "profiles")
     for f in rec["sources"]:
         dst = tmp_path / f
         os.makedirs(dst.parent, exist_ok=True)
         shutil.copy(os.path.join(ROOT, f), dst)
+    rec2 = dict(rec, source_sha256_16=_sources_hash(str(tmp_path), rec["sources"]))
+    with open(tmp_path / "profiles" / "qd_gemm_2048_counters.json", "w") as fh:
+        json.dump(rec2, fh)
     bench.ROOT = str(tmp_path)
     assert bench.measured_traffic("qd_gemm_2048") == rec["traffic_bytes"]
     with open(tmp_path / rec["sources"][0], "ab") as fh:

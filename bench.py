@@ -137,7 +137,9 @@ def gemm_row(mpx, torch, T, p, n, reps):
     A = gpu_mp(torch, K, (n, n), synth.seed_for(1, 0), dtype=dt)
     B = gpu_mp(torch, K, (n, n), synth.seed_for(1, 1), dtype=dt)
     Cm = torch.empty_like(A)
-    v, _ = mpx.gemm_autotune(p, A, B, Cm, reps=1)
+    # three calls per sample: single calls of the short products (FF, DD,
+    # n <= 1024) ranked tilings a few percent apart in either order
+    v, _ = mpx.gemm_autotune(p, A, B, Cm, reps=3)
     ms = T(lambda: mpx.gemm(p, A, B, out=Cm), reps=reps)
     macs = float(n) ** 3
     peak = PEAK_F32_ISSUE if p == "ff" else PEAK_F64_ISSUE
@@ -677,7 +679,7 @@ def main():
                           "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE}}), flush=True)
         return
     if args.only:
-        fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd")},
+        fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048, reps=3) for q in ("qd", "td", "dd", "ff")},
               "gemv": lambda: gemv_rows(mpx, torch, T),
               "vector": lambda: vector_rows(mpx, torch, T),
               "vector_sweep": lambda: vector_sweep_rows(mpx, torch, T),

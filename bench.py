@@ -209,8 +209,10 @@ def vector_rows(mpx, torch, T):
             r = torch.empty(K, dtype=torch.float64, device="cuda")
             ws = mpx.workspace(mpx.OP_DOT, p, n)
             reps = 200 if n == 4096 else 10
-            t_axpy = T(lambda: mpx.axpy(p, alpha, x, y), reps=reps)
-            t_dot = T(lambda: mpx.dot(p, x, y, out=r, ws=ws), reps=reps)
+            # best of three batches: one stall inside a batch of short calls
+            # would otherwise dominate its mean
+            t_axpy = min(T(lambda: mpx.axpy(p, alpha, x, y), reps=reps) for _ in range(3))
+            t_dot = min(T(lambda: mpx.dot(p, x, y, out=r, ws=ws), reps=reps) for _ in range(3))
             b_axpy, b_dot = 3 * K * 8.0 * n, 2 * K * 8.0 * n
             row[str(n)] = {
                 "axpy_us": t_axpy * 1e3, "axpy_GB_s": b_axpy / (t_axpy * 1e-3) / 1e9,
@@ -230,7 +232,7 @@ def vector_rows(mpx, torch, T):
                     with torch.cuda.graph(g):
                         for _ in range(calls):
                             fn()
-                    tg = T(lambda: g.replay(), reps=10) / calls
+                    tg = min(T(lambda: g.replay(), reps=10) for _ in range(3)) / calls
                     row[str(n)][f"{name}_graph_us"] = tg * 1e3
                     row[str(n)][f"{name}_graph_calls_per_s"] = 1.0 / (tg * 1e-3)
                     del g

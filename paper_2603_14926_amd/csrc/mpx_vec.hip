@@ -19,6 +19,25 @@ namespace mpx {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
+// Streaming access to data touched once per call (the vectors of the
+// elementwise ops, AXPY and dot, the matrix of GEMV): nontemporal loads and
+// stores, which streamed 3-16 % faster on MI355X at n = 2^24 .. 2^26 than
+// plain ones.  The values are the same; only the cache policy differs.
+template <typename T, int K>
+__device__ __forceinline__ mpn<T, K> mp_load_stream(const T* base, long long ps, long long idx) {
+    mpn<T, K> r;
+#pragma unroll
+    for (int i = 0; i < K; ++i) r.c[i] = __builtin_nontemporal_load(&base[i * ps + idx]);
+    return r;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void mp_store_stream(T* base, long long ps, long long idx,
+                                                const mpn<T, K>& v) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) __builtin_nontemporal_store(v.c[i], &base[i * ps + idx]);
+}
+
 // ------------------------------------------------------------ elementwise --
 
 // AR selects the branch-free (0) or conventional (1, 2) operations.
@@ -28,12 +47,12 @@ k_elementwise(long long n, const T* x, long long psx, const T* y, long long psy,
               long long psz) {
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const mpn<T, K> a = mp_load<T, K>(x, psx, i);
-        const mpn<T, K> b = mp_load<T, K>(y, psy, i);
+        const mpn<T, K> a = mp_load_stream<T, K>(x, psx, i);
+        const mpn<T, K> b = mp_load_stream<T, K>(y, psy, i);
         mpn<T, K> c;
         if constexpr (OP == 0) c = ar_add<AR>(a, b);
         else c = ar_mul<AR>(a, b);
-        mp_store<T, K>(z, psz, i, c);
+        mp_store_stream<T, K>(z, psz, i, c);
     }
 }
 
@@ -43,9 +62,9 @@ k_axpy(long long n, mpn<T, K> alpha, const T* __restrict__ x, long long psx, T* 
        long long psy) {
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const mpn<T, K> a = mp_load<T, K>(x, psx, i);
-        const mpn<T, K> b = mp_load<T, K>(y, psy, i);
-        mp_store<T, K>(y, psy, i, ar_add<AR>(ar_mul<AR>(alpha, a), b));
+        const mpn<T, K> a = mp_load_stream<T, K>(x, psx, i);
+        const mpn<T, K> b = mp_load_stream<T, K>(y, psy, i);
+        mp_store_stream<T, K>(y, psy, i, ar_add<AR>(ar_mul<AR>(alpha, a), b));
     }
 }
 
@@ -120,7 +139,8 @@ k_dot_partial(long long n, const T* __restrict__ x, long long psx, const T* __re
     const long long stride = (long long)gridDim.x * kBlock;
     mpn<T, K> acc = mp_zero<T, K>();
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        acc = ar_add<AR>(acc, ar_mul<AR>(mp_load<T, K>(x, psx, i), mp_load<T, K>(y, psy, i)));
+        acc = ar_add<AR>(acc, ar_mul<AR>(mp_load_stream<T, K>(x, psx, i),
+                                         mp_load_stream<T, K>(y, psy, i)));
     acc = block_sum<T, K, AR>(acc);
     if (threadIdx.x == 0) mp_store<T, K>(out, pso, blockIdx.x, acc);
 }
@@ -201,7 +221,8 @@ k_gemv_n(long long m, long long n, const T* __restrict__ A, long long lda, long 
         for (int u = 0; u < U; ++u) {
             xv[u] = mp_load<T, K>(x, psx, j + 64 * u);
 #pragma unroll
-            for (int r = 0; r < R; ++r) av[u][r] = mp_load<T, K>(A, psA, rows[r] * lda + j + 64 * u);
+            for (int r = 0; r < R; ++r)
+                av[u][r] = mp_load_stream<T, K>(A, psA, rows[r] * lda + j + 64 * u);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -212,7 +233,7 @@ k_gemv_n(long long m, long long n, const T* __restrict__ A, long long lda, long 
         const mpn<T, K> xv = mp_load<T, K>(x, psx, j);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            acc[r] = bf_add(acc[r], bf_mul(mp_load<T, K>(A, psA, rows[r] * lda + j), xv));
+            acc[r] = bf_add(acc[r], bf_mul(mp_load_stream<T, K>(A, psA, rows[r] * lda + j), xv));
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -234,7 +255,7 @@ k_gemv_t(long long m, long long n, const T* __restrict__ A, long long lda, long 
     const long long i1 = i0 + chunk < m ? i0 + chunk : m;
     mpn<T, K> acc = mp_zero<T, K>();
     for (long long i = i0; i < i1; ++i)
-        acc = bf_add(acc, bf_mul(mp_load<T, K>(A, psA, i * lda + j), mp_load<T, K>(x, psx, i)));
+        acc = bf_add(acc, bf_mul(mp_load_stream<T, K>(A, psA, i * lda + j), mp_load<T, K>(x, psx, i)));
     mp_store<T, K>(out, pso, blockIdx.y * n + j, acc);
 }
 

@@ -66,3 +66,27 @@ def test_cpu_baseline_fields():
     assert r["kind"] == "oracle" and r["unit"] == "mp-op/s"
     assert r["value"] > 0 and 1 <= r["cores"] <= 16
     assert "QD GEMM rows 0.." in r["sample"] and "64x64x64" in r["sample"]
+
+
+def test_bench_exact_dot_matches_the_exact_checker():
+    """The benchmark's own exact sum of products (used for the Ozaki error
+    comparison, so the timed script needs nothing from the oracle) equals the
+    exact-rational checker's, and the relative error it reports is that of
+    the checker."""
+    import numpy as np
+    from oracle import exact
+    from paper_2603_14926_amd import synth
+    bench = _bench()
+    for K, n, dist in ((2, 300, "W"), (4, 257, "U"), (3, 1, "U")):
+        a = synth.mp_array(K, n, 70 + K, dist)
+        b = synth.mp_array(K, n, 80 + K, dist)
+        assert bench.exact_dot(a, b) == exact.dot(a, b)
+    A = synth.mp_array(2, (5, 64), 91, "W", phi=8.0)
+    B = synth.mp_array(2, (64, 4), 92, "W", phi=8.0)
+    C = np.zeros((2, 5, 4))
+    C[0] = A[0] @ B[0]                                   # binary64 product: a visible error
+    rows, cols = np.array([0, 3, 4]), np.array([1, 0, 3])
+    want = max(float(abs(exact.value(C[:, i, j]) - exact.dot(np.ascontiguousarray(A[:, i, :]),
+                                                                np.ascontiguousarray(B[:, :, j]))))
+               / exact.abs_dot(A[:, i, :], B[:, :, j]) for i, j in zip(rows, cols))
+    assert bench.rel_errors(A, B, C, rows, cols) == want

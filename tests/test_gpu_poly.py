@@ -58,6 +58,64 @@ def test_dk_iterations_bit_exact_from_same_start(p, K):
         assert np.array_equal(to_np(st), wst)
 
 
+# High degrees of the benchmark mix (16..512) beside small ones.  The packed
+# schedule caps a job at the largest polynomial spread over four waves, so the
+# degree-512 and degree-384 polynomials each put two 64-root chunks on one
+# wave, and the small ones are packed around them.
+HIGH = [512, 16, 384, 20, 257, 33, 511, 64, 300, 65, 17, 129, 448, 5]
+
+
+def _max_horner_exponent(deg, z0r, z0i):
+    """Largest n log2|z| over the start values: the exponent E that Horner's
+    power-of-two rescaling reaches on the first sweep."""
+    _, roff = synth.offsets(deg)
+    e = 0.0
+    for b, n in enumerate(deg):
+        z = np.abs(z0r[0, roff[b]:roff[b + 1]] + 1j * z0i[0, roff[b]:roff[b + 1]])
+        e = max(e, float(n) * float(np.log2(z.max())))
+    return e
+
+
+@pytest.mark.parametrize("p,K", PRECS)
+def test_dk_high_degree_bit_exact_every_variant(p, K):
+    """Degrees up to 512 from the oracle's Aberth start values, 3 sweeps, on
+    every launch variant.  The start radius is ~n |c_{n-1}|, so E reaches
+    thousands of bits on the first sweep and the scaled coefficients
+    c_k 2^-E pass through the subnormal range to zero: those ldexp results
+    must round as the oracle's do."""
+    deg, cre, cim = _dk_inputs(K, HIGH, 70 + K)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    assert _max_horner_exponent(deg, z0r, z0i) > 1100   # c_k 2^-E underflows on the way
+    wr, wi, wst = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=3, init=False)
+    gc_r, gc_i = to_gpu(cre), to_gpu(cim)
+    for v in range(mpx.polyroots_variant_count()):
+        plan = mpx.RootsPlan(p, deg, iters=3, init=False, graph=False)
+        plan.set_variant(v)
+        zr, zi = to_gpu(z0r), to_gpu(z0i)
+        st = plan.run(gc_r, gc_i, zr, zi)
+        assert bits_equal(to_np(zr), wr), (v, first_mismatch(to_np(zr), wr))
+        assert bits_equal(to_np(zi), wi), v
+        assert np.array_equal(to_np(st), wst), v
+
+
+def test_dk_degree_512_200_sweeps_bit_exact():
+    """One degree-512 QD polynomial (with two small ones) over the benchmark's
+    200 sweeps in a graph-replayed packed launch, bit for bit."""
+    K = 4
+    deg, cre, cim = _dk_inputs(K, [512, 24, 61], 90)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, wst = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=200, init=False)
+    plan = mpx.RootsPlan("qd", deg, iters=200, init=False, graph=True)
+    zr, zi = to_gpu(z0r), to_gpu(z0i)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        st = plan.run(to_gpu(cre), to_gpu(cim), zr, zi)
+    stream.synchronize()
+    assert bits_equal(to_np(zr), wr), first_mismatch(to_np(zr), wr)
+    assert bits_equal(to_np(zi), wi)
+    assert np.array_equal(to_np(st), wst)
+
+
 def test_dk_odd_and_even_iteration_counts_and_resume():
     K = 4
     deg, cre, cim = _dk_inputs(K, [7, 33, 2, 64], 20)
@@ -211,7 +269,8 @@ def test_dk_full_batch_sampled_bit_exact():
 
 @pytest.mark.parametrize("p,K", PRECS)
 @pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023), (8, 2047),
-                                       (1024, 2047)])
+                                       (1024, 2047), (5, 2048), (3, 3000), (4, 4095), (3, 4096), (2, 8191),
+                                       (1024, 4095)])
 def test_estrin_bit_exact(p, K, batch, deg):
     coef = synth.mp_array(K, (batch, deg + 1), 80 + deg, "U")
     x = synth.mp_array(K, batch, 81 + deg, "U")
@@ -220,8 +279,8 @@ def test_estrin_bit_exact(p, K, batch, deg):
     assert bits_equal(got, want), first_mismatch(got, want)
 
 
-def test_estrin_rejects_degree_beyond_2047():
-    coef = torch.zeros((4, 2, 2049), dtype=torch.float64, device="cuda")
+def test_estrin_rejects_degree_beyond_8191():
+    coef = torch.zeros((4, 2, 8193), dtype=torch.float64, device="cuda")
     x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(mpx.MpxError):
         mpx.polyval("qd", coef, x, method="estrin")
@@ -229,7 +288,7 @@ def test_estrin_rejects_degree_beyond_2047():
 
 @pytest.mark.parametrize("p,K", PRECS)
 @pytest.mark.parametrize("batch,deg", [(1, 0), (3, 1), (5, 2), (70, 63), (9, 64), (33, 100), (64, 1023),
-                                       (1024, 1023)])
+                                       (1024, 1023), (3, 1024), (4, 2047), (2, 3001), (3, 4095)])
 def test_polyval_cplx_bit_exact(p, K, batch, deg):
     """Real-coefficient polynomials at complex points, Horner and Estrin."""
     coef = synth.mp_array(K, (batch, deg + 1), 90 + deg, "U")
@@ -255,9 +314,9 @@ def test_polyval_cplx_conventional_bit_exact(p, K, mode):
 
 
 def test_polyval_cplx_estrin_limits():
-    coef = torch.zeros((4, 2, 1025), dtype=torch.float64, device="cuda")
+    coef = torch.zeros((4, 2, 4097), dtype=torch.float64, device="cuda")
     x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(mpx.MpxError):
-        mpx.polyval_cplx("qd", coef, x, x.clone(), method="estrin")          # degree 1024
+        mpx.polyval_cplx("qd", coef, x, x.clone(), method="estrin")          # degree 4096
     with pytest.raises(mpx.MpxError):
         mpx.polyval_cplx("qd_nobf", coef[:, :, :4].contiguous(), x, x.clone(), method="estrin")

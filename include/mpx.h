@@ -288,8 +288,10 @@ int mpx_polyval(int prec, int64_t batch, int64_t deg, const void *coef, int64_t 
  * Estrin): the coefficient list of each polynomial is padded with zeros to
  * N = 2^L >= deg+1 entries; level l = 1..L replaces it by
  * c'_j = c_{2j} + c_{2j+1} X_{l-1} (BF multiply, then BF add), X_0 = x,
- * X_l = X_{l-1}^2.  One wave per polynomial; deg <= 2047 (else
- * MPX_ENOTSUP).  Same layout and errors as mpx_polyval. */
+ * X_l = X_{l-1}^2.  One wave per polynomial up to deg 2047, one
+ * four-wave workgroup per polynomial for deg 2048..8191 (at most 32
+ * coefficients per lane either way); deg >= 8192 gives MPX_ENOTSUP.  Same
+ * layout and errors as mpx_polyval. */
 int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,
                        const void *x, int64_t psx, void *y, int64_t psy, void *stream);
 
@@ -301,7 +303,8 @@ int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const void *coef, i
  * the real part only (arithmetic flags accepted); method 1 = Estrin's list
  * halving, whose first level pairs real coefficients,
  * c' = (a_2j + a_2j+1 Re x, a_2j+1 Im x), later levels c' = c_2j + c_2j+1 X
- * with X := X^2 per level (branch-free only, deg <= 1023, else
+ * with X := X^2 per level (branch-free only; one wave per polynomial up
+ * to deg 1023, a four-wave workgroup for deg 1024..4095; deg >= 4096 gives
  * MPX_ENOTSUP).  Bit-identical to the sequential definitions; y must not
  * alias the inputs. */
 int mpx_polyval_cplx(int prec, int64_t batch, int64_t deg, const void *coef, int64_t psc,

@@ -148,6 +148,61 @@ k_estrin(long long batch, long long deg, int L, const double* __restrict__ coef,
     if (lane == 0) mp_store<double, K>(y, psy, b, c);
 }
 
+// Estrin for the long lists (N = 2^L, L = LB + 8): one 256-thread workgroup
+// per polynomial, so a lane still holds at most 2^LB <= 32 coefficients.
+// Thread t owns the block of B = 2^LB coefficients from t B; levels 1..LB
+// run lane-locally as above, the next six across the lanes of each wave,
+// and the last two combine the four waves' values (waves 0..3 hold the
+// level LB + 6 entries 0..3) through LDS in the same pairing order.
+template <int K, int LB>
+__global__ void __launch_bounds__(256)
+k_estrin_wg(long long deg, const double* __restrict__ coef, long long psc,
+            const double* __restrict__ x, long long psx, double* __restrict__ y, long long psy) {
+    using V = mpn<double, K>;
+    constexpr int B = 1 << LB;
+    const long long b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long off = b * (deg + 1);
+    __shared__ double s_top[4][K];
+    V st[LB + 1];
+    V Xl[LB + 1];
+    Xl[0] = mp_load<double, K>(x, psx, b);
+#pragma unroll
+    for (int l = 1; l <= LB; ++l) Xl[l] = bf_mul(Xl[l - 1], Xl[l - 1]);
+    EstrinLocal<K, LB, 0>::run(st, Xl, coef, psc, (long long)threadIdx.x * B, deg, off);
+    V c = st[LB];
+    V Xc = Xl[LB];
+#pragma unroll
+    for (int lev = 0; lev < 6; ++lev) {
+        const int sft = 1 << lev;
+        V other;
+#pragma unroll
+        for (int q = 0; q < K; ++q) other.c[q] = __shfl_down(c.c[q], sft, 64);
+        const V comb = bf_add(c, bf_mul(other, Xc));
+        const bool leader = (lane & (2 * sft - 1)) == 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) c.c[q] = leader ? comb.c[q] : c.c[q];
+        Xc = bf_mul(Xc, Xc);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) s_top[wv][q] = c.c[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        V v[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int q = 0; q < K; ++q) v[w].c[q] = s_top[w][q];
+        const V lo = bf_add(v[0], bf_mul(v[1], Xc));
+        const V hi = bf_add(v[2], bf_mul(v[3], Xc));
+        Xc = bf_mul(Xc, Xc);
+        mp_store<double, K>(y, psy, b, bf_add(lo, bf_mul(hi, Xc)));
+    }
+}
+
 // Gradients of L = sum_b g_b p_b(x_b):
 //   dL/da_{b,i} = t_i with t_0 = g_b, t_{i+1} = t_i * x_b   (adjoint of Horner)
 //   dL/dx_b     = g_b * d, d from  d := d * x + h  before  h := h * x + a_i
@@ -414,6 +469,70 @@ k_estrin_cplx(long long batch, long long deg, int L, const double* __restrict__ 
     if (lane == 0) c_store<K>(yre, yim, psy, b, c);
 }
 
+// Complex-point Estrin for the long lists (N = 2^L, L = LB + 8, LB >= 1):
+// one 256-thread workgroup per polynomial, lane-local levels as in
+// k_estrin_cplx (the first pairs real coefficients), six levels across the
+// lanes of each wave, the last two across the four waves through LDS.
+template <int K, int LB>
+__global__ void __launch_bounds__(256)
+k_estrin_cplx_wg(long long deg, const double* __restrict__ coef, long long psc,
+                 const double* __restrict__ xre, const double* __restrict__ xim, long long psx,
+                 double* __restrict__ yre, double* __restrict__ yim, long long psy) {
+    static_assert(LB >= 1, "the first level must be lane-local");
+    using C = cplx<K>;
+    constexpr int B = 1 << LB;
+    const long long b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long off = b * (deg + 1);
+    __shared__ double s_top[4][2][K];
+    C Xl[LB + 1];
+    Xl[0] = c_load<K>(xre, xim, psx, b);
+#pragma unroll
+    for (int l = 1; l <= LB; ++l) Xl[l] = c_mul<K>(Xl[l - 1], Xl[l - 1]);
+    mpn<double, K> st0;
+    C st[LB + 1];
+    EstrinCplxLocal<K, LB, 0>::run(st0, st, Xl, coef, psc, (long long)threadIdx.x * B, deg, off);
+    C c = st[LB];
+    C Xc = Xl[LB];
+#pragma unroll
+    for (int lev = 0; lev < 6; ++lev) {
+        const int sft = 1 << lev;
+        C other;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            other.re.c[q] = __shfl_down(c.re.c[q], sft, 64);
+            other.im.c[q] = __shfl_down(c.im.c[q], sft, 64);
+        }
+        const C comb = c_add<K>(c, c_mul<K>(other, Xc));
+        const bool leader = (lane & (2 * sft - 1)) == 0;
+        c = c_select<K>(leader, comb, c);
+        Xc = c_mul<K>(Xc, Xc);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            s_top[wv][0][q] = c.re.c[q];
+            s_top[wv][1][q] = c.im.c[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        C v[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                v[w].re.c[q] = s_top[w][0][q];
+                v[w].im.c[q] = s_top[w][1][q];
+            }
+        const C lo = c_add<K>(v[0], c_mul<K>(v[1], Xc));
+        const C hi = c_add<K>(v[2], c_mul<K>(v[3], Xc));
+        Xc = c_mul<K>(Xc, Xc);
+        c_store<K>(yre, yim, psy, b, c_add<K>(lo, c_mul<K>(hi, Xc)));
+    }
+}
+
 // ------------------------------------------------------ Durand-Kerner ----
 
 struct DkPlanDev {
@@ -668,6 +787,135 @@ k_dk_packed(DkPlanDev P, double* rre, double* rim, long long psr, int* status, i
     }
 }
 
+// Lane-packed schedule: a job's polynomials (descending degree, with small
+// ones filling lanes its larger ones leave idle) have their roots laid out
+// over 64-lane items; an item's lanes may belong to several polynomials, and
+// its loops run to the largest degree among them (a lane stops at its own
+// degree).  Items of (job j, wave w) are wave_off[j W + w] ..
+// wave_off[j W + w + 1] - 1.
+struct DkLaneSched {
+    const int* wave_off;   // njobs W + 1 entries
+    const int* item_len;   // per item: loop length
+    const int2* lanes;     // per item: 64 (polynomial, root index), polynomial -1 = idle lane
+    const int* poly_off;   // njobs + 1: polynomials of job j are polys[poly_off[j] .. poly_off[j+1]-1]
+    const int* polys;
+    int njobs;
+};
+
+// One DK update of root idx of polynomial b (b < 0: an idle lane, which loads
+// and stores nothing) inside an item whose loops run len steps: the same
+// Horner and root-difference product as dk_roots, each step taken only
+// while the step index is below the lane's own degree.
+template <int K, int AR>
+__device__ __forceinline__ void dk_root_lane(const DkPlanDev& P, int b, int idx, int len,
+                                             const double* sre, const double* sim, long long pss,
+                                             double* dre, double* dim, long long psd) {
+    using C = cplx<K>;
+    const bool live = b >= 0;
+    const int n = live ? P.degree[b] : 0;
+    const long long co = live ? P.coef_off[b] : 0;
+    const long long ro = live ? P.root_off[b] : 0;
+    C z;
+    z.re = mp_zero<double, K>();
+    z.im = mp_zero<double, K>();
+    if (live) z = c_load<K>(sre, sim, pss, ro + idx);
+    C h;
+    h.re = mp_from<double, K>(1.0);
+    h.im = mp_zero<double, K>();
+    long long E = 0;
+#pragma nounroll
+    for (int k = len - 1; k >= 0; --k) {
+        if (k < n) {
+            const C ck = c_load<K>(P.mre, P.mim, P.psm, co + k);
+            h = c_add<K, AR>(c_mul<K, AR>(h, z), c_ldexp<K>(ck, clamp_exp(-E)));
+            c_rescale<K, true>(h, E);
+        }
+    }
+    C Pp;
+    Pp.re = mp_from<double, K>(1.0);
+    Pp.im = mp_zero<double, K>();
+    long long F = 0;
+#pragma nounroll
+    for (int j = 0; j < len; ++j) {
+        if (j < n) {
+            const C zj = c_load<K>(sre, sim, pss, ro + j);
+            C t = c_mul<K, AR>(Pp, c_sub<K, AR>(z, zj));
+            long long Ft = F;
+            c_rescale<K, false>(t, Ft);
+            const bool take = j != idx;
+            Pp = c_select<K>(take, t, Pp);
+            F = take ? Ft : F;
+        }
+    }
+    if (live) {
+        const C w = c_ldexp<K>(c_div<K, AR>(h, Pp), clamp_exp(E - F));
+        c_store<K>(dre, dim, psd, ro + idx, c_sub<K, AR>(z, w));
+    }
+}
+
+// Lane-packed persistent kernel: W-wave workgroups pull jobs (heaviest
+// first) and sweep their items; the barrier after each sweep orders sweep
+// t's writes before sweep t + 1's reads for every polynomial of the job, and
+// every thread runs the same number of barriers (job index, iters and
+// status are uniform).  The copy-back of an odd sweep count and the status
+// flags go over the job's polynomial list, one polynomial per wave at a time.
+template <int K, int AR, int W>
+__global__ void __launch_bounds__(64 * W)
+k_dk_lanes(DkPlanDev P, DkLaneSched S, double* rre, double* rim, long long psr, int* status,
+           int iters) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __shared__ int s_slot;
+    for (;;) {
+        if (threadIdx.x == 0) s_slot = atomicAdd(P.counter, 1);
+        __syncthreads();
+        const int slot = s_slot;
+        __syncthreads();  // all have read s_slot before it is overwritten
+        if (slot >= S.njobs) break;  // the same value in every thread: uniform exit
+        const int i0 = S.wave_off[slot * W + wv], i1 = S.wave_off[slot * W + wv + 1];
+        for (int it = 0; it < iters; ++it) {
+            const bool from_user = (it & 1) == 0;
+            const double* sre = from_user ? rre : P.zre;
+            const double* sim = from_user ? rim : P.zim;
+            double* dre = from_user ? P.zre : rre;
+            double* dim = from_user ? P.zim : rim;
+            const long long pss = from_user ? psr : P.psz;
+            const long long psd = from_user ? P.psz : psr;
+            for (int i = i0; i < i1; ++i) {
+                const int2 e = S.lanes[64LL * i + lane];
+                dk_root_lane<K, AR>(P, e.x, e.y, S.item_len[i], sre, sim, pss, dre, dim, psd);
+            }
+            __syncthreads();  // iterate t complete before t+1 reads it
+        }
+        const int q0 = S.poly_off[slot], q1 = S.poly_off[slot + 1];
+        if (iters & 1) {  // result is in the plan buffer: copy the job's roots back
+            for (int q = q0 + wv; q < q1; q += W) {
+                const int b = S.polys[q], n = P.degree[b];
+                const long long ro = P.root_off[b];
+                for (int r = lane; r < n; r += 64)
+                    c_store<K>(rre, rim, psr, ro + r, c_load<K>(P.zre, P.zim, P.psz, ro + r));
+            }
+            __syncthreads();
+        }
+        if (status) {
+            for (int q = q0 + wv; q < q1; q += W) {
+                const int b = S.polys[q], n = P.degree[b];
+                const long long ro = P.root_off[b];
+                int bad = 0;
+                for (int r = lane; r < n; r += 64) {
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        bad |= !isfinite(rre[c * psr + ro + r]) || !isfinite(rim[c * psr + ro + r]);
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+                if (lane == 0) status[b] = bad;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- plan ----
 
 struct DkVariant {
@@ -819,6 +1067,16 @@ static int estrin_t(long long batch, long long deg, const void* coef, long long 
                     long long psx, void* y, long long psy, hipStream_t s) {
     int L = 0;
     while (L < 62 && (1LL << L) < deg + 1) ++L;  // beyond the supported depths: ENOTSUP below
+    if (L >= 12) {  // 4 waves per polynomial, 2^(L-8) coefficients per lane
+        if (L > 13 || batch > INT32_MAX) return MPX_ENOTSUP;
+        if (L == 12)
+            k_estrin_wg<K, 4><<<(unsigned)batch, 256, 0, s>>>(deg, (const double*)coef, psc,
+                                                              (const double*)x, psx, (double*)y, psy);
+        else
+            k_estrin_wg<K, 5><<<(unsigned)batch, 256, 0, s>>>(deg, (const double*)coef, psc,
+                                                              (const double*)x, psx, (double*)y, psy);
+        return launch_status();
+    }
     const int LB = L > 6 ? L - 6 : 0;
     const unsigned blocks = (unsigned)ceil_div(batch, 4);
 #define MPX_ES(LBV)                                                                             \
@@ -840,6 +1098,18 @@ static int estrin_cplx_t(long long batch, long long deg, const void* coef, long 
                          long long psy, hipStream_t s) {
     int L = 0;
     while (L < 62 && (1LL << L) < deg + 1) ++L;  // beyond the supported depths: ENOTSUP below
+    if (L >= 11) {  // 4 waves per polynomial, 2^(L-8) coefficients per lane
+        if (L > 12 || batch > INT32_MAX) return MPX_ENOTSUP;
+        if (L == 11)
+            k_estrin_cplx_wg<K, 3><<<(unsigned)batch, 256, 0, s>>>(
+                deg, (const double*)coef, psc, (const double*)xre, (const double*)xim, psx,
+                (double*)yre, (double*)yim, psy);
+        else
+            k_estrin_cplx_wg<K, 4><<<(unsigned)batch, 256, 0, s>>>(
+                deg, (const double*)coef, psc, (const double*)xre, (const double*)xim, psx,
+                (double*)yre, (double*)yim, psy);
+        return launch_status();
+    }
     const int LB = L > 6 ? L - 6 : 0;
     const unsigned blocks = (unsigned)ceil_div(batch, 4);
 #define MPX_EC(LBV)                                                                            \
@@ -876,7 +1146,7 @@ extern "C" int mpx_polyval_cplx(int prec, int64_t batch, int64_t deg, const void
     }
     hipStream_t s = as_stream(stream);
     if (method == 1) {
-        if (deg >= 1024) return MPX_ENOTSUP;  // 16 coefficients per lane at most
+        if (deg >= 4096) return MPX_ENOTSUP;  // 16 coefficients per lane at most
         switch (prec) {
             case MPX_DD: return estrin_cplx_t<2>(batch, deg, coef, psc, xre, xim, psx, yre, yim, psy, s);
             case MPX_TD: return estrin_cplx_t<3>(batch, deg, coef, psc, xre, xim, psx, yre, yim, psy, s);
@@ -913,10 +1183,9 @@ extern "C" int mpx_polyval_estrin(int prec, int64_t batch, int64_t deg, const vo
     if (poly_out_overlaps(prec, y, vec_bytes(prec, batch, psy), batch, deg, coef, psc, x, nullptr,
                           nullptr, psx))
         return MPX_EINVAL;
-    // degree >= 2048 would need 64 coefficients per lane; the QD build of that
-    // shape exceeds the register file and its results did not match the
-    // sequential definition, so it is not offered
-    if (deg >= 2048) return MPX_ENOTSUP;
+    // degrees 2048..8191 run four waves per polynomial (at most 32
+    // coefficients per lane); longer lists are not offered
+    if (deg >= 8192) return MPX_ENOTSUP;
     hipStream_t s = as_stream(stream);
     switch (prec) {
         case MPX_DD: return estrin_t<2>(batch, deg, coef, psc, x, psx, y, psy, s);

@@ -62,10 +62,12 @@ def test_traffic_only_from_counters_on_current_sources(tmp_path):
 
 def test_cpu_baseline_fields():
     bench = _bench()
-    r = bench.cpu_baseline("qd", 64, target_s=0.05)
+    r = bench.cpu_baseline("qd", 64, target_s=0.05, target_1t_s=0.05)
     assert r["kind"] == "oracle" and r["unit"] == "mp-op/s"
     assert r["value"] > 0 and 1 <= r["cores"] <= 16
     assert "QD GEMM rows 0.." in r["sample"] and "64x64x64" in r["sample"]
+    one = r["single_thread"]
+    assert one["cores"] == 1 and one["value"] > 0 and one["unit"] == "mp-op/s"
 
 
 def test_bench_exact_dot_matches_the_exact_checker():
@@ -86,7 +88,21 @@ def test_bench_exact_dot_matches_the_exact_checker():
     C = np.zeros((2, 5, 4))
     C[0] = A[0] @ B[0]                                   # binary64 product: a visible error
     rows, cols = np.array([0, 3, 4]), np.array([1, 0, 3])
-    want = max(float(abs(exact.value(C[:, i, j]) - exact.dot(np.ascontiguousarray(A[:, i, :]),
-                                                                np.ascontiguousarray(B[:, :, j]))))
-               / exact.abs_dot(A[:, i, :], B[:, :, j]) for i, j in zip(rows, cols))
-    assert bench.rel_errors(A, B, C, rows, cols) == want
+    d = [abs(exact.value(C[:, i, j]) - exact.dot(np.ascontiguousarray(A[:, i, :]),
+                                                 np.ascontiguousarray(B[:, :, j]))) for i, j in zip(rows, cols)]
+    want_sum = max(float(e) / exact.abs_dot(A[:, i, :], B[:, :, j]) for e, i, j in zip(d, rows, cols))
+    want_rel = max(float(e / abs(exact.dot(np.ascontiguousarray(A[:, i, :]), np.ascontiguousarray(B[:, :, j]))))
+                   for e, i, j in zip(d, rows, cols))
+    import torch
+    got = bench.ExactSample(A, B, rows, cols).errors(torch, torch.from_numpy(C))
+    assert got == {"sum_norm": want_sum, "rel": want_rel}
+
+
+def test_bench_sampled_entries_cover_tile_edges():
+    import numpy as np
+    bench = _bench()
+    rows, cols = bench.sampled_entries(4096, 64, np.random.default_rng(0))
+    assert rows.size == cols.size == 64
+    for e in (0, 15, 16, 31, 32, 2047, 2048, 4095):
+        assert e in rows[:18] and e in cols[:18]
+    assert rows.min() >= 0 and rows.max() < 4096 and cols.min() >= 0 and cols.max() < 4096

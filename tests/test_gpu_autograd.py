@@ -3,7 +3,8 @@ QD / DD GEMM (dA = dC B^T, dB = A^T dC) and Horner (coefficient and x
 gradients), against the oracle gradient (bit-exact: same kernels' sequential
 order) and against central finite differences evaluated by the oracle in
 the same precision (the GEMM and the coefficient map are linear, so the
-difference quotient has no truncation error)."""
+difference quotient has no truncation error; for the x-gradient the step is
+small enough that its truncation error lies far below the tolerance)."""
 from fractions import Fraction
 
 import numpy as np
@@ -71,16 +72,17 @@ def test_gemm_backward_finite_differences_qd():
     assert abs(exact.value(dB[:, 2, 4]) - ex) <= Fraction(m * 2.0 ** -208) * Fraction(exact.abs_dot(A[:, :, 2], G[:, :, 4]))
 
 
-def test_gemm_backward_2048_sampled():
-    """config size: QD GEMM 2048 forward + backward through autograd, sampled
-    entries of C, dA, dB checked bit for bit against the oracle."""
-    K, n = 4, 2048
+@pytest.mark.parametrize("p,K", [("qd", 4), ("dd", 2)])
+def test_gemm_backward_2048_sampled(p, K):
+    """config size: QD and DD GEMM 2048 forward + backward through autograd,
+    sampled entries of C, dA, dB checked bit for bit against the oracle."""
+    n = 2048
     A = synth.mp_array(K, (n, n), synth.seed_for(3, 0), "U")
     B = synth.mp_array(K, (n, n), synth.seed_for(3, 1), "U")
     G = synth.mp_array(K, (n, n), synth.seed_for(3, 2), "U")
     tA = to_gpu(A).requires_grad_(True)
     tB = to_gpu(B).requires_grad_(True)
-    Cm = ag.gemm(tA, tB, "qd")
+    Cm = ag.gemm(tA, tB, p)
     Cm.backward(to_gpu(G))
     rows = np.array([0, 17, 1024, 2047]); cols = np.array([5, 2047, 1023, 0])
     assert bits_equal(to_np(Cm.detach())[:, rows, cols], oracle.gemm_entries(K, A, B, rows, cols))
@@ -128,3 +130,31 @@ def test_polyval_coefficient_gradient_finite_differences():
         want = exact.value(fd)
         got = exact.value(grad[:, b, i])
         assert abs(got - want) <= Fraction(2.0 ** -160) * (1 + abs(want))
+
+
+def test_polyval_x_gradient_finite_differences_and_exact_derivative():
+    """x-gradient of Horner in QD against (i) central differences
+    (p(x + h) - p(x - h)) / 2h evaluated by the oracle in QD with h = 2^-70,
+    whose truncation error h^2 |p'''| / 6 stays below 2^-120 relative, and
+    (ii) the exact derivative sum_i i a_i x^(i-1) in rational arithmetic."""
+    K, batch, deg = 4, 6, 30
+    coef = synth.mp_array(K, (batch, deg + 1), 22, "U")
+    x = synth.mp_array(K, batch, 23, "U")
+    g = np.zeros((K, batch)); g[0] = 1.0
+    tx = to_gpu(x).requires_grad_(True)
+    ag.polyval(to_gpu(coef), tx, "qd").backward(to_gpu(g))
+    gx = to_np(tx.grad)
+    h = 2.0 ** -70
+    step = np.array([h, 0.0, 0.0, 0.0])
+    xp = np.stack([oracle.op1(K, "add", x[:, b], step) for b in range(batch)], 1)
+    xm = np.stack([oracle.op1(K, "add", x[:, b], -step) for b in range(batch)], 1)
+    yp, ym = oracle.polyval(K, coef, xp), oracle.polyval(K, coef, xm)
+    for b in range(batch):
+        fd = oracle.op1(K, "add", yp[:, b], -ym[:, b]) / (2 * h)   # exact power-of-two scaling
+        want = exact.value(fd)
+        got = exact.value(gx[:, b])
+        assert abs(got - want) <= Fraction(2.0 ** -120) * (1 + abs(want)), b
+        xv = exact.value(x[:, b])
+        terms = [i * exact.value(coef[:, b, i]) * xv ** (i - 1) for i in range(1, deg + 1)]
+        d = sum(terms)
+        assert abs(got - d) <= Fraction(2.0 ** -200) * (1 + sum(abs(t) for t in terms)), b

@@ -84,3 +84,28 @@ def test_ozaki_block_exponents_bit_exact(kblk, k):
     rows, cols = np.divmod(np.arange(m * n), n)
     want = oracle.ozaki_entries(A, B, rows, cols, s=5, beta=21, kblk=kblk).reshape(2, m, n)
     assert bits_equal(got, want), first_mismatch(got, want)
+
+
+@pytest.fixture
+def oz_variant():
+    """Stage-depth variant of the slice GEMM, restored to the default after."""
+    yield mpx.gemm_ozaki_set_variant
+    mpx.gemm_ozaki_set_variant(0)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("s,beta,kblk", [(s, 20, 64) for s in range(1, 13)] +
+                         [(4, 22, 256), (5, 22, 256), (6, 22, 256)])
+@pytest.mark.parametrize("mnk", [(70, 45, 300), (129, 97, 530)])
+def test_ozaki_every_slice_count_and_stage_variant(oz_variant, variant, s, beta, kblk, mnk):
+    """Every slice count 1..12, the benchmark's exact (slices, 22, 256)
+    choices, and both LDS stage depths (8 and 16 k per stage), at shapes
+    ragged against the 32-row / 32-column MFMA tiles and the k-blocks."""
+    m, n, k = mnk
+    oz_variant(variant)
+    A = synth.mp_array(2, (m, k), 1100 + 13 * s + kblk, "W", phi=4.0)
+    B = synth.mp_array(2, (k, n), 1200 + 13 * s + kblk, "W", phi=4.0)
+    got = to_np(mpx.gemm_ozaki_dd(to_gpu(A), to_gpu(B), s, beta=beta, kblk=kblk))
+    rows, cols = np.divmod(np.arange(m * n), n)
+    want = oracle.ozaki_entries(A, B, rows, cols, s=s, beta=beta, kblk=kblk).reshape(2, m, n)
+    assert bits_equal(got, want), (variant, first_mismatch(got, want))

@@ -125,18 +125,28 @@ enum { MPX_OP_DOT = 1, MPX_OP_GEMV = 2, MPX_OP_GEMM = 3, MPX_OP_OZAKI = 4, MPX_O
  * allowed).  Returns 0 for invalid arguments. */
 size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k, int64_t extra);
 
-/* result[0..K-1] (device, K contiguous values) = sum_i x_i * y_i.
+/* result[0..K-1] (device, K contiguous values) = sum_i x_i * y_i: the inner
+ * product of the basic linear computations the paper accelerates (Section 1
+ * and the BF operations of Section 2 inside the linear kernels of Section 3;
+ * the paper benchmarks the matrix products built from them and defines no
+ * separate inner-product routine, so the plain sum is the definition).
  * Per-thread partial sums are sequential BF multiply-adds; partials are
  * combined with BF additions in a fixed tree.  Error <= n * 2^-b *
- * sum |x_i y_i| with b = 104 / 155 / 208 (FF: 46).  ws: device workspace of
- * at least mpx_workspace_size(MPX_OP_DOT, prec, n, 0, 0, 0) bytes. */
+ * sum |x_i y_i| with b = 104 / 155 / 208 (FF: 46).  One launch: the block
+ * that finishes last (an integer ticket in the workspace) adds the block
+ * partials.  ws: device workspace of at least mpx_workspace_size(MPX_OP_DOT,
+ * prec, n, 0, 0, 0) bytes (0 for n <= 256); its contents need no
+ * initialisation (every call tags the ticket with its own generation), but
+ * calls that share one workspace must not overlap in time. */
 int mpx_dot(int prec, int64_t n, const void *x, int64_t psx, const void *y, int64_t psy,
             void *result, void *ws, size_t ws_bytes, void *stream);
 
-/* y = op(A) x, A an m x n row-major matrix with leading dimension lda >= n
- * and plane stride psA >= m*lda; op(A) = A (trans = 0, y has m entries) or
- * A^T (trans = 1, y has n entries).  Same error bound as mpx_dot with the
- * row length in place of n. */
+/* y = op(A) x, the matrix-vector product of the same basic linear layer
+ * (Sections 1 and 3; no separate definition in the paper, so the plain sums
+ * are the definition).  A is an m x n row-major matrix with leading
+ * dimension lda >= n and plane stride psA >= m*lda; op(A) = A (trans = 0, y
+ * has m entries) or A^T (trans = 1, y has n entries).  Same error bound as
+ * mpx_dot with the row length in place of n. */
 int mpx_gemv(int prec, int trans, int64_t m, int64_t n, const void *A, int64_t lda,
              int64_t psA, const void *x, int64_t psx, void *y, int64_t psy, void *ws,
              size_t ws_bytes, void *stream);
@@ -222,9 +232,23 @@ int mpx_gemm_plan_destroy(mpx_gemm_plan plan);
 /* ---------------------------------------------------------- GEMM tuning --
  * The GEMM has several register/LDS tilings ("variants"); all produce the
  * same bits.  mpx_gemm picks one per (precision, transposes, log2 size
- * bucket): the autotuned choice if mpx_gemm_autotune ran for that bucket in
- * this process, else the largest tile that still gives >= 2048 workgroups. */
+ * bucket): a tiling named in the environment variable MPX_GEMM_VARIANT
+ * (comma-separated names; the first that belongs to the precision), else
+ * the tuned choice for that bucket, else the largest tile that still gives
+ * >= 2048 workgroups.  Tuned choices come from mpx_gemm_autotune in this
+ * process and, when MPX_TUNE_CACHE names a file, from that file, which every
+ * autotune rewrites (lines "<gfx arch> gemm <prec> <tA> <tB> <log2 m> <log2 n>
+ * <log2 k> <tiling name>"; lines of other GPUs are kept).  MPX_TUNE=off
+ * ignores tuned choices.  The root solver's plans use the same cache for
+ * their launch variant ("<arch> dk <prec> <log2 batch> <log2 max degree>
+ * <variant>"), with MPX_DK_VARIANT=<index> forcing one. */
 int mpx_gemm_variant_count(int prec);
+/* The variant mpx_gemm would use for this shape now (>= 0), or a negative
+ * status for invalid arguments (m, n >= 1). */
+int mpx_gemm_selected_variant(int prec, int transA, int transB, int64_t m, int64_t n, int64_t k);
+/* Re-read the tune-cache file named by MPX_TUNE_CACHE (no file: empty),
+ * replacing this process's tuned choices. */
+int mpx_tune_reload(void);
 const char *mpx_gemm_variant_name(int prec, int variant);   /* NULL if out of range */
 /* mpx_gemm with an explicit variant; same arguments and errors otherwise. */
 int mpx_gemm_variant(int prec, int variant, int transA, int transB, int64_t m, int64_t n,
@@ -334,20 +358,29 @@ int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef,
  *
  * Layout: polynomial b has degree[b] >= 1; its coefficients a_0..a_n are
  * columns coef_off[b] .. coef_off[b] + n of the K planes of coef_re and
- * coef_im, where coef_off = prefix sums of (degree + 1); its roots are columns
- * root_off[b] .. root_off[b] + n - 1 of roots_re / roots_im (prefix sums of
- * degree).  roots_* hold the start values on entry (unless MPX_DK_INIT) and
- * the iterate on return; passing them back resumes the iteration exactly.
+ * coef_im; its roots are columns root_off[b] .. root_off[b] + n - 1 of
+ * roots_re / roots_im.  coef_off_host and root_off_host (host arrays of
+ * batch + 1 entries, copied by the constructor) give the offsets; both NULL
+ * means packed prefix sums (coef_off[0] = 0, coef_off[b+1] = coef_off[b] +
+ * degree[b] + 1; root_off likewise with degree[b]).  Given offsets need
+ * coef_off[0], root_off[0] >= 0, coef_off[b+1] - coef_off[b] >= degree[b] + 1
+ * and root_off[b+1] - root_off[b] >= degree[b] (so polynomials never share a
+ * column; gaps are allowed and left untouched), and at most 2^40 columns;
+ * the planes then span coef_off[batch] and root_off[batch] columns.  Only
+ * one of the two NULL is MPX_EINVAL.  roots_* hold the start values on entry
+ * (unless MPX_DK_INIT) and the iterate on return; passing them back resumes
+ * the iteration exactly.
  * status[b] (nullable) = 0 if all roots of b are finite, 1 otherwise (e.g.
  * coincident start values).
  *
- * A plan is created outside graph capture; it allocates its device schedule
- * (polynomials in descending-degree order for load balance, and the packed
- * 4-wave jobs) and working buffers (monic coefficients, second iterate) and
- * frees them in mpx_plan_destroy.  The constructor returns MPX_EINVAL for a
- * degree below 1 or unknown flags, MPX_ENOTSUP when the batch holds more than
- * 2^29 - 1 chunks of 64 roots, MPX_EDEVICE when a host or device allocation
- * fails.  With
+ * A plan is created outside graph capture; it allocates its device
+ * schedules (polynomials in descending-degree order for load balance, the
+ * packed 4-wave jobs, and the lane-packed jobs of every lane-packed variant)
+ * and working buffers (monic coefficients, second iterate) and frees them in
+ * mpx_plan_destroy.  The constructor returns MPX_EINVAL for a degree below 1,
+ * invalid offsets or unknown flags, MPX_ENOTSUP when a schedule's int
+ * indices would overflow (about 2^24 items of 64 roots), MPX_EDEVICE when a
+ * host or device allocation fails.  With
  * MPX_DK_GRAPH and a non-NULL stream, mpx_polyroots captures its launches
  * into a HIP graph on first use and replays it while buffers and stream stay
  * the same; on a stream the caller is already capturing it launches
@@ -356,21 +389,29 @@ int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const void *coef,
 typedef struct mpx_plan_s *mpx_plan;
 enum { MPX_DK_INIT = 1, MPX_DK_GRAPH = 2 };
 int mpx_polyroots_plan(mpx_plan *out, int prec, int64_t batch, const int32_t *degree_host,
-                       int iters, uint32_t flags);
+                       const int64_t *coef_off_host, const int64_t *root_off_host, int iters,
+                       uint32_t flags);
 int mpx_polyroots(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
                   void *roots_re, void *roots_im, int64_t psr, int32_t *status, void *stream);
 int mpx_plan_destroy(mpx_plan plan);
-/* Launch-shape variants (roots per lane, resident waves per CU, or the packed
+/* Launch-shape variants (roots per lane, resident waves per CU, the packed
  * schedule: 4-wave jobs built by the plan, each holding whole polynomials
- * whose 64-root chunks are spread over the waves to balance their loads);
- * results do not depend on the variant.  A new plan uses the packed schedule
- * with 8 resident waves per CU.  The autotuner runs each for iters_probe sweeps
+ * whose 64-root chunks are spread over the waves to balance their loads, or
+ * a lane-packed schedule: 4-, 8- or 12-wave jobs whose roots are laid out
+ * lane by lane over 64-lane items, so roots of several polynomials share a
+ * wave and small polynomials fill lanes a larger one leaves idle); results
+ * do not depend on the variant.  A new plan uses the packed schedule with 8
+ * resident waves per CU, or the variant the tune cache holds for its
+ * (precision, batch, largest degree) bucket, or MPX_DK_VARIANT (see the GEMM
+ * tuning notes).  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants
  * (a variant's time is its faster round), switches the plan to the fastest
  * only when it beats the plan's current variant by at least 3 %, and returns
- * the index kept (or a negative status).  Synchronises; allocates. */
+ * the index kept (or a negative status), which it also records in the tune
+ * cache.  Synchronises; allocates. */
 int mpx_polyroots_variant_count(void);
 int mpx_polyroots_set_variant(mpx_plan plan, int variant);
+int mpx_polyroots_get_variant(mpx_plan plan);   /* the plan's current variant */
 int mpx_polyroots_autotune(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
                            const void *roots_re, const void *roots_im, int64_t psr,
                            int iters_probe, float *best_ms, void *stream);

@@ -32,6 +32,9 @@
 #include "mpx_internal.hpp"
 
 #include <algorithm>
+#include <string>
+#include <cstdlib>
+#include <cstdio>
 #include <mutex>
 #include <new>
 #include <map>
@@ -277,18 +280,25 @@ static const std::vector<Variant>& variants(int prec) {
 #undef MPX_TILES_TD
 #undef MPX_TILES_QD
 
-// Tuned choices, keyed by (prec, tA, tB, log2 buckets of m, n, k).
-using TuneKey = std::tuple<int, int, int, int, int, int>;
-static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune;
-
+// Tuned choices, keyed by (prec, tA, tB, log2 buckets of m, n, k), live in
+// the tune cache as "gemm <prec> <tA> <tB> <bm> <bn> <bk>" -> tiling name.
 static int ilog2_bucket(long long v) {
     int b = 0;
     while ((1LL << (b + 1)) <= v) ++b;
     return b;
 }
-static TuneKey tune_key(int prec, const GemmArgs& g) {
-    return TuneKey(prec, g.tA, g.tB, ilog2_bucket(g.m), ilog2_bucket(g.n), ilog2_bucket(g.k));
+static std::string tune_key(int prec, const GemmArgs& g) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "gemm %d %d %d %d %d %d", prec, g.tA, g.tB, ilog2_bucket(g.m),
+                  ilog2_bucket(g.n), ilog2_bucket(g.k));
+    return buf;
+}
+
+static int variant_by_name(int prec, const std::string& name) {
+    const auto& v = variants(prec);
+    for (size_t i = 0; i < v.size(); ++i)
+        if (name == v[i].name) return (int)i;
+    return -1;
 }
 
 // Untuned default: the largest tile that still yields at least 2048
@@ -302,10 +312,25 @@ static int default_variant(int prec, const GemmArgs& g) {
     return (int)v.size() - 1;
 }
 
+// A tiling forced by MPX_GEMM_VARIANT (comma-separated names), else the tuned
+// choice for this bucket, else the size heuristic.
 static int pick_variant(int prec, const GemmArgs& g) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(prec, g));
-    return it != g_tune.end() ? it->second : default_variant(prec, g);
+    if (const char* f = std::getenv("MPX_GEMM_VARIANT")) {
+        std::string names(f);
+        size_t pos = 0;
+        while (pos <= names.size()) {
+            const size_t end = std::min(names.find(',', pos), names.size());
+            const int v = variant_by_name(prec, names.substr(pos, end - pos));
+            if (v >= 0) return v;
+            pos = end + 1;
+        }
+    }
+    std::string choice;
+    if (tune_lookup(tune_key(prec, g), choice)) {
+        const int v = variant_by_name(prec, choice);
+        if (v >= 0) return v;
+    }
+    return default_variant(prec, g);
 }
 
 static int check_gemm(int prec, int tA, int tB, int64_t m, int64_t n, int64_t k, const void* A,
@@ -342,6 +367,17 @@ extern "C" int mpx_gemm(int prec, int transA, int transB, int64_t m, int64_t n, 
     if (m == 0 || n == 0) return MPX_OK;
     GemmArgs g{(int)m, (int)n, (int)k, transA, transB, A, lda, psA, B, ldb, psB, C, ldc, psC};
     return variants(prec)[pick_variant(prec, g)].fn(g, as_stream(stream));
+}
+
+// The tiling mpx_gemm would use for this shape (forced, tuned or default).
+extern "C" int mpx_gemm_selected_variant(int prec, int transA, int transB, int64_t m, int64_t n,
+                                         int64_t k) {
+    if (!prec_k_ar(prec)) return MPX_EPREC;
+    if (m < 1 || n < 1 || k < 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2 ||
+        (transA != 0 && transA != 1) || (transB != 0 && transB != 1))
+        return MPX_EINVAL;
+    GemmArgs g{(int)m, (int)n, (int)k, transA, transB, nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0};
+    return pick_variant(prec, g);
 }
 
 // Number of kernel variants available for a precision, and their names.
@@ -396,19 +432,14 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
             if (best < 0 || ms < best_t) { best = v; best_t = ms; }
         }
     if (st) return st;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[tune_key(prec, g)] = best;
-    }
+    tune_store(tune_key(prec, g), vs[best].name);
     if (best_ms) *best_ms = best_t;
     return best;
 }
 
-// Forget all tuned choices (back to the size heuristic).
-extern "C" void mpx_gemm_autotune_reset(void) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune.clear();
-}
+// Forget this process's tuned GEMM choices (back to the size heuristic); the
+// cache file, if any, is left as it is.
+extern "C" void mpx_gemm_autotune_reset(void) { tune_forget("gemm"); }
 
 // ------------------------------------------------------- batched GEMM ----
 //

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "../../include/mpx.h"
 
@@ -110,4 +111,11 @@ size_t gemv_workspace(int prec, long long m, long long n, int trans);
 size_t ozaki_workspace(long long m, long long n, long long k, int slices);
 size_t cgemm_workspace(int prec, long long m, long long n, long long k);
 size_t strassen_workspace(int prec, long long m, long long n, long long k, long long cutoff);
+
+// Tuned launch choices (mpx_tune.hip): in-process, and in the MPX_TUNE_CACHE
+// file when that is set.  Keys are "<op> <fields...>", choices one word.
+bool tune_disabled();
+bool tune_lookup(const std::string& op_key, std::string& choice);
+void tune_store(const std::string& op_key, const std::string& choice);
+void tune_forget(const std::string& op);
 }  // namespace mpx

@@ -34,8 +34,12 @@
 #include "mp_arith.hpp"
 #include "mp_conv.hpp"
 #include "mpx_internal.hpp"
+#include "dk_sched.hpp"
 
 #include <algorithm>
+#include <string>
+#include <cstdlib>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
@@ -207,36 +211,70 @@ k_estrin_wg(long long deg, const double* __restrict__ coef, long long psc,
 //   dL/da_{b,i} = t_i with t_0 = g_b, t_{i+1} = t_i * x_b   (adjoint of Horner)
 //   dL/dx_b     = g_b * d, d from  d := d * x + h  before  h := h * x + a_i
 // (d = 0, h = a_deg initially).  Either output may be null.
+//
+// The chains run in separate waves, 128-thread blocks, one polynomial per
+// lane.  Coefficient blocks (the first ncb blocks when gcoef is requested):
+// both waves run t-chains for 128 polynomials.  x blocks: 64 polynomials;
+// wave 0 runs the Horner chain h and hands every pre-update h to wave 1
+// through LDS, wave 1 runs the d chain on them, one chunk of kBwdChunk
+// steps behind (double-buffered, a barrier per chunk), so the x gradient
+// costs about one Horner pass instead of two.
+constexpr int kBwdChunk = 8;
+
 template <int K>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
 k_polyval_bwd(long long batch, long long deg, const double* __restrict__ coef, long long psc,
               const double* __restrict__ x, long long psx, const double* __restrict__ g,
               long long psg, double* __restrict__ gcoef, long long psgc,
-              double* __restrict__ gx, long long psgx) {
+              double* __restrict__ gx, long long psgx, unsigned ncb) {
     using V = mpn<double, K>;
-    const long long b = (long long)blockIdx.x * 64 + threadIdx.x;
-    if (b >= batch) return;
-    const long long off = b * (deg + 1);
-    const V xv = mp_load<double, K>(x, psx, b);
-    const V gv = mp_load<double, K>(g, psg, b);
-    if (gcoef) {
-        V t = gv;
+    if (blockIdx.x < ncb) {  // coefficient gradients
+        const long long b = (long long)blockIdx.x * 128 + threadIdx.x;
+        if (b >= batch) return;
+        const long long off = b * (deg + 1);
+        const V xv = mp_load<double, K>(x, psx, b);
+        V t = mp_load<double, K>(g, psg, b);
         mp_store<double, K>(gcoef, psgc, off, t);
         for (long long i = 1; i <= deg; ++i) {
             t = bf_mul(t, xv);
             mp_store<double, K>(gcoef, psgc, off + i, t);
         }
+        return;
     }
-    if (gx) {
-        V h = mp_load<double, K>(coef, psc, off + deg);
-        V d = mp_zero<double, K>();
-        for (long long i = deg - 1; i >= 0; --i) {
-            const V a = mp_load<double, K>(coef, psc, off + i);
-            d = bf_add(bf_mul(d, xv), h);
-            h = bf_add(bf_mul(h, xv), a);
+    // x gradients; the whole block stays to the end (it meets every barrier)
+    __shared__ double hbuf[2][kBwdChunk][K][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long long b = (long long)(blockIdx.x - ncb) * 64 + lane;
+    const bool live = b < batch;
+    const long long bb = live ? b : 0;
+    const long long off = bb * (deg + 1);
+    const V xv = mp_load<double, K>(x, psx, bb);
+    const long long nch = (deg + kBwdChunk - 1) / kBwdChunk;  // chunks of steps
+    V h = mp_load<double, K>(coef, psc, off + deg);           // wave 0's Horner value
+    V d = mp_zero<double, K>();                               // wave 1's derivative
+    for (long long t = 0; t <= nch; ++t) {
+        if (wv == 0 && t < nch) {  // steps t C .. t C + C - 1 (i = deg - 1 - step)
+            const long long s0 = t * kBwdChunk;
+            const int cnt = (int)(deg - s0 < kBwdChunk ? deg - s0 : kBwdChunk);
+            for (int j = 0; j < cnt; ++j) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) hbuf[t & 1][j][c][lane] = h.c[c];
+                h = bf_add(bf_mul(h, xv), mp_load<double, K>(coef, psc, off + deg - 1 - s0 - j));
+            }
         }
-        mp_store<double, K>(gx, psgx, b, bf_mul(gv, d));
+        if (wv == 1 && t > 0) {    // the chunk wave 0 wrote one round earlier
+            const long long s0 = (t - 1) * kBwdChunk;
+            const int cnt = (int)(deg - s0 < kBwdChunk ? deg - s0 : kBwdChunk);
+            for (int j = 0; j < cnt; ++j) {
+                V hs;
+#pragma unroll
+                for (int c = 0; c < K; ++c) hs.c[c] = hbuf[(t - 1) & 1][j][c][lane];
+                d = bf_add(bf_mul(d, xv), hs);
+            }
+        }
+        __syncthreads();  // chunk t written before it is read; chunk t-1 read before reuse
     }
+    if (wv == 1 && live) mp_store<double, K>(gx, psgx, b, bf_mul(mp_load<double, K>(g, psg, b), d));
 }
 
 // ------------------------------------------------- complex arithmetic ----
@@ -918,14 +956,24 @@ k_dk_lanes(DkPlanDev P, DkLaneSched S, double* rre, double* rim, long long psr, 
 
 // ---------------------------------------------------------------- plan ----
 
+enum { DK_WAVE = 0, DK_PACKED = 1, DK_LANES = 2 };
+
 struct DkVariant {
-    int r;          // roots per lane processed together
+    int r;          // roots per lane processed together (one-wave kernel)
     int waves_cu;   // resident waves per CU targeted by the grid size
-    bool packed;    // 4-wave jobs of the packed schedule (r = 1)
+    int kind;       // DK_WAVE: a wave per polynomial; DK_PACKED: 4-wave jobs of
+                    // 64-root chunks; DK_LANES: W-wave jobs of lane-packed items
+    int w;          // waves per job (DK_LANES)
+    int lscale;     // job cap, percent of the largest polynomial's heaviest wave (DK_LANES)
+    int sched;      // index of the plan's lane-packed schedule (DK_LANES)
 };
-static const DkVariant kDkVariants[] = {{1, 8, false}, {2, 8, false}, {1, 16, false},
-                                        {2, 12, false}, {1, 8, true}, {1, 12, true}};
+static const DkVariant kDkVariants[] = {
+    {1, 8, DK_WAVE, 1, 0, -1},    {2, 8, DK_WAVE, 1, 0, -1},    {1, 16, DK_WAVE, 1, 0, -1},
+    {2, 12, DK_WAVE, 1, 0, -1},   {1, 8, DK_PACKED, 4, 0, -1},  {1, 12, DK_PACKED, 4, 0, -1},
+    {1, 8, DK_LANES, 4, 150, 0},  {1, 8, DK_LANES, 8, 150, 1},  {1, 8, DK_LANES, 8, 200, 2},
+    {1, 12, DK_LANES, 12, 200, 3}};
 constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
+constexpr int kDkLaneScheds = 4;
 
 }  // namespace mpx
 
@@ -934,10 +982,13 @@ struct mpx_plan_s {
     int prec = 0, K = 0, batch = 0, iters = 0;
     unsigned flags = 0;
     int variant = 4;                // the packed schedule, 8 waves per CU (kDkVariants[4])
+    int max_degree = 0;
     long long total_coef = 0, total_roots = 0;
     int cus = 256;
     void* dev = nullptr;            // one allocation: schedule + offsets + buffers
     mpx::DkPlanDev d{};
+    void* lane_dev[mpx::kDkLaneScheds] = {};   // lane-packed schedules, one allocation each
+    mpx::DkLaneSched lane[mpx::kDkLaneScheds] = {};
     // graph cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -949,13 +1000,14 @@ struct mpx_plan_s {
 
 namespace mpx {
 
-template <int K, int R, int AR, bool PACKED>
-static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long long psc, void* rre,
-                       void* rim, long long psr, int* status, int waves_cu, hipStream_t s) {
+template <int K, int R, int AR, int KIND, int W>
+static int launch_dk_t(mpx_plan_s* p, const DkVariant& v, const void* are, const void* aim,
+                       long long psc, void* rre, void* rim, long long psr, int* status,
+                       hipStream_t s) {
     k_reset_counter<<<1, 1, 0, s>>>(p->d.counter);
     int st = launch_status();
     if (st) return st;
-    long long grid = (long long)p->cus * waves_cu;
+    long long grid = (long long)p->cus * v.waves_cu;
     if (grid > p->batch) grid = p->batch;
     if (grid < 1) grid = 1;
     k_dk_prologue<K, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (const double*)are,
@@ -963,12 +1015,19 @@ static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long lon
                                                   (double*)rim, psr,
                                                   (p->flags & MPX_DK_INIT) ? 1 : 0);
     if ((st = launch_status())) return st;
-    if constexpr (PACKED) {
-        long long groups = (long long)p->cus * waves_cu / kDkPackedWaves;
+    if constexpr (KIND == DK_PACKED) {
+        long long groups = (long long)p->cus * v.waves_cu / kDkPackedWaves;
         if (groups > p->d.njobs) groups = p->d.njobs;
         if (groups < 1) groups = 1;
         k_dk_packed<K, AR><<<(unsigned)groups, 64 * kDkPackedWaves, 0, s>>>(
             p->d, (double*)rre, (double*)rim, psr, status, p->iters);
+    } else if constexpr (KIND == DK_LANES) {
+        const DkLaneSched& S = p->lane[v.sched];
+        long long groups = (long long)p->cus * v.waves_cu / W;
+        if (groups > S.njobs) groups = S.njobs;
+        if (groups < 1) groups = 1;
+        k_dk_lanes<K, AR, W><<<(unsigned)groups, 64 * W, 0, s>>>(p->d, S, (double*)rre,
+                                                              (double*)rim, psr, status, p->iters);
     } else {
         k_durand_kerner<K, R, AR><<<(unsigned)grid, 64, 0, s>>>(p->batch, p->d, (double*)rre,
                                                             (double*)rim, psr, status, p->iters);
@@ -978,15 +1037,27 @@ static int launch_dk_t(mpx_plan_s* p, const void* are, const void* aim, long lon
 
 static int launch_dk(mpx_plan_s* p, int variant, const void* are, const void* aim, long long psc,
                      void* rre, void* rim, long long psr, int* status, hipStream_t s) {
-    const DkVariant v = kDkVariants[variant];
-#define MPX_DK_CASE(KK, AR_)                                                                   \
-    if (p->K == KK && ar == AR_) {                                                             \
-        if (v.packed) return launch_dk_t<KK, 1, AR_, true>(p, are, aim, psc, rre, rim, psr,   \
-                                                           status, v.waves_cu, s);             \
-        if (v.r == 1) return launch_dk_t<KK, 1, AR_, false>(p, are, aim, psc, rre, rim, psr,  \
-                                                            status, v.waves_cu, s);            \
-        return launch_dk_t<KK, 2, AR_, false>(p, are, aim, psc, rre, rim, psr, status,        \
-                                              v.waves_cu, s);                                  \
+    const DkVariant& v = kDkVariants[variant];
+#define MPX_DK_CASE(KK, AR_)                                                                  \
+    if (p->K == KK && ar == AR_) {                                                            \
+        if (v.kind == DK_PACKED)                                                              \
+            return launch_dk_t<KK, 1, AR_, DK_PACKED, 4>(p, v, are, aim, psc, rre, rim, psr,  \
+                                                         status, s);                          \
+        if (v.kind == DK_LANES) {                                                             \
+            if (v.w == 4)                                                                     \
+                return launch_dk_t<KK, 1, AR_, DK_LANES, 4>(p, v, are, aim, psc, rre, rim,    \
+                                                            psr, status, s);                  \
+            if (v.w == 8)                                                                     \
+                return launch_dk_t<KK, 1, AR_, DK_LANES, 8>(p, v, are, aim, psc, rre, rim,    \
+                                                            psr, status, s);                  \
+            return launch_dk_t<KK, 1, AR_, DK_LANES, 12>(p, v, are, aim, psc, rre, rim, psr,  \
+                                                         status, s);                          \
+        }                                                                                     \
+        if (v.r == 1)                                                                         \
+            return launch_dk_t<KK, 1, AR_, DK_WAVE, 1>(p, v, are, aim, psc, rre, rim, psr,    \
+                                                       status, s);                            \
+        return launch_dk_t<KK, 2, AR_, DK_WAVE, 1>(p, v, are, aim, psc, rre, rim, psr,        \
+                                                   status, s);                                \
     }
     const int ar = arith_of(p->prec);
     MPX_DK_CASE(2, AR_BF)
@@ -1217,12 +1288,13 @@ extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const 
                 return MPX_EINVAL;
         if (overlaps(gcoef, gcb, gx, gxb)) return MPX_EINVAL;
     }
-    const unsigned blocks = (unsigned)ceil_div(batch, 64);
+    const unsigned ncb = gcoef ? (unsigned)ceil_div(batch, 128) : 0u;
+    const unsigned grid = ncb + (gx ? (unsigned)ceil_div(batch, 64) : 0u);
     hipStream_t s = as_stream(stream);
 #define MPX_PB(KK)                                                                             \
-    k_polyval_bwd<KK><<<blocks, 64, 0, s>>>(batch, deg, (const double*)coef, psc,              \
-                                            (const double*)x, psx, (const double*)gy, psg,     \
-                                            (double*)gcoef, psgc, (double*)gx, psgx)
+    k_polyval_bwd<KK><<<grid, 128, 0, s>>>(batch, deg, (const double*)coef, psc,               \
+                                           (const double*)x, psx, (const double*)gy, psg,      \
+                                           (double*)gcoef, psgc, (double*)gx, psgx, ncb)
     switch (prec) {
         case MPX_DD: MPX_PB(2); break;
         case MPX_TD: MPX_PB(3); break;
@@ -1232,22 +1304,82 @@ extern "C" int mpx_polyval_backward(int prec, int64_t batch, int64_t deg, const 
     return launch_status();
 }
 
+// Tune-cache key of a plan: precision, log2 buckets of batch and largest degree.
+static std::string dk_tune_key(const mpx_plan_s* p) {
+    auto lg = [](long long v) { int b = 0; while ((2LL << b) <= v) ++b; return b; };
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "dk %d %d %d", p->prec, lg(std::max(p->batch, 1)),
+                  lg(std::max(p->max_degree, 1)));
+    return buf;
+}
+
+// Variant a new plan starts on: MPX_DK_VARIANT if it names a valid index,
+// else the tuned choice for its bucket, else the packed schedule.
+static int dk_start_variant(const mpx_plan_s* p) {
+    if (const char* f = std::getenv("MPX_DK_VARIANT")) {
+        char* end = nullptr;
+        const long v = std::strtol(f, &end, 10);
+        if (end != f && *end == '\0' && v >= 0 && v < kDkVariantCount) return (int)v;
+    }
+    std::string choice;
+    if (tune_lookup(dk_tune_key(p), choice)) {
+        char* end = nullptr;
+        const long v = std::strtol(choice.c_str(), &end, 10);
+        if (end != choice.c_str() && *end == '\0' && v >= 0 && v < kDkVariantCount) return (int)v;
+    }
+    return 4;
+}
+
+extern "C" int mpx_plan_destroy(mpx_plan p) {
+    if (!p) return MPX_OK;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->dev) (void)hipFree(p->dev);
+    for (void* q : p->lane_dev)
+        if (q) (void)hipFree(q);
+    delete p;
+    return MPX_OK;
+}
+
+// Columns of the coefficient and root planes are limited to 2^40 so every
+// buffer size and offset stays far from int64 overflow.
+constexpr long long kDkMaxColumns = 1LL << 40;
+
 static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t* degree_host,
-                          int iters, uint32_t flags) {
+                          const int64_t* coef_off_host, const int64_t* root_off_host, int iters,
+                          uint32_t flags) {
     if (out == nullptr) return MPX_EINVAL;
     *out = nullptr;
     if (!prec_k_ar(prec) || base_prec(prec) == MPX_FF) return MPX_EPREC;
     if (batch < 0 || batch > INT32_MAX || (degree_host == nullptr && batch > 0) || iters < 0)
         return MPX_EINVAL;
     if (flags & ~(uint32_t)(MPX_DK_INIT | MPX_DK_GRAPH)) return MPX_EINVAL;
+    if ((coef_off_host == nullptr) != (root_off_host == nullptr)) return MPX_EINVAL;
+    const bool given = coef_off_host != nullptr;
     std::vector<int> deg(batch), order(batch);
     std::vector<long long> coff(batch + 1), roff(batch + 1);
-    coff[0] = roff[0] = 0;
+    coff[0] = given ? coef_off_host[0] : 0;
+    roff[0] = given ? root_off_host[0] : 0;
+    if (coff[0] < 0 || roff[0] < 0 || coff[0] > kDkMaxColumns || roff[0] > kDkMaxColumns)
+        return MPX_EINVAL;
     for (int64_t b = 0; b < batch; ++b) {
         if (degree_host[b] < 1) return MPX_EINVAL;
         deg[b] = degree_host[b];
-        coff[b + 1] = coff[b] + deg[b] + 1;
-        roff[b + 1] = roff[b] + deg[b];
+        if (given) {
+            // polynomial b owns columns [coef_off[b], coef_off[b+1]) and
+            // [root_off[b], root_off[b+1]): room for its n + 1 coefficients and
+            // n roots, no overlap with its neighbours
+            const long long c1 = coef_off_host[b + 1], r1 = root_off_host[b + 1];
+            if (c1 > kDkMaxColumns || r1 > kDkMaxColumns || c1 - coff[b] < (long long)deg[b] + 1 ||
+                r1 - roff[b] < (long long)deg[b])
+                return MPX_EINVAL;
+            coff[b + 1] = c1;
+            roff[b + 1] = r1;
+        } else {
+            coff[b + 1] = coff[b] + deg[b] + 1;
+            roff[b + 1] = roff[b] + deg[b];
+            if (coff[b + 1] > kDkMaxColumns) return MPX_EINVAL;
+        }
         order[b] = (int)b;
     }
     // longest-processing-time order: descending n^2 (ties: index order)
@@ -1331,6 +1463,21 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
         }
     }
 
+    int cus = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    // Lane-packed schedules, one per DK_LANES variant (slots: jobs resident at once)
+    LaneSchedHost lsh[kDkLaneScheds];
+    for (const DkVariant& v : kDkVariants) {
+        if (v.kind != DK_LANES) continue;
+        const long long slots = std::max<long long>(1, (long long)cus * v.waves_cu / v.w);
+        if (!build_lane_sched(deg, v.w, v.lscale / 100.0, slots, lsh[v.sched])) return MPX_ENOTSUP;
+    }
+
     auto* p = new (std::nothrow) mpx_plan_s();
     if (!p) return MPX_EDEVICE;
     p->prec = prec;
@@ -1340,10 +1487,9 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
     p->flags = flags;
     p->total_coef = coff[batch];
     p->total_roots = roff[batch];
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-        p->cus = prop.multiProcessorCount;
+    p->cus = cus;
+    for (int d : deg) p->max_degree = std::max(p->max_degree, d);
+    p->variant = dk_start_variant(p);
 
     const size_t n_i = (size_t)batch, K = (size_t)p->K;
     const size_t sz_order = n_i * sizeof(int), sz_deg = n_i * sizeof(int);
@@ -1381,6 +1527,35 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
     const long long psz = std::max<long long>(p->total_roots, 1);
     p->d = DkPlanDev{d_order, d_deg, d_coff, d_roff, d_m, d_m + K * psm, d_z, d_z + K * psz,
                      d_cnt, psm, psz, d_jo, d_it, (int)(job_off.size() - 1)};
+    for (int i = 0; i < kDkLaneScheds; ++i) {
+        const LaneSchedHost& h = lsh[i];
+        const size_t b_wo = h.wave_off.size() * sizeof(int), b_il = std::max<size_t>(h.item_len.size(), 1) * sizeof(int);
+        const size_t b_ln = std::max<size_t>(h.lanes.size(), 2) * sizeof(int);
+        const size_t b_po = h.poly_off.size() * sizeof(int), b_pl = std::max<size_t>(h.polys.size(), 1) * sizeof(int);
+        if (hipMalloc(&p->lane_dev[i], al(b_wo) + al(b_il) + al(b_ln) + al(b_po) + al(b_pl)) != hipSuccess) {
+            mpx_plan_destroy(p);
+            return MPX_EDEVICE;
+        }
+        c = (char*)p->lane_dev[i];
+        int* wo = (int*)take(b_wo);
+        int* il = (int*)take(b_il);
+        int2* ln = (int2*)take(b_ln);
+        int* po = (int*)take(b_po);
+        int* pl = (int*)take(b_pl);
+        e = hipMemcpy(wo, h.wave_off.data(), b_wo, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !h.item_len.empty())
+            e = hipMemcpy(il, h.item_len.data(), h.item_len.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !h.lanes.empty())
+            e = hipMemcpy(ln, h.lanes.data(), h.lanes.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(po, h.poly_off.data(), b_po, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !h.polys.empty())
+            e = hipMemcpy(pl, h.polys.data(), h.polys.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            mpx_plan_destroy(p);
+            return MPX_EDEVICE;
+        }
+        p->lane[i] = DkLaneSched{wo, il, ln, po, pl, h.njobs};
+    }
     *out = p;
     return MPX_OK;
 }
@@ -1388,22 +1563,17 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
 // Host allocation failures (the schedule's vectors, all made before the plan
 // itself) end as MPX_EDEVICE: no exception crosses the C boundary.
 extern "C" int mpx_polyroots_plan(mpx_plan* out, int prec, int64_t batch,
-                                  const int32_t* degree_host, int iters, uint32_t flags) {
+                                  const int32_t* degree_host, const int64_t* coef_off_host,
+                                  const int64_t* root_off_host, int iters, uint32_t flags) {
     try {
-        return polyroots_plan(out, prec, batch, degree_host, iters, flags);
+        return polyroots_plan(out, prec, batch, degree_host, coef_off_host, root_off_host, iters,
+                              flags);
     } catch (const std::bad_alloc&) {
         return MPX_EDEVICE;
     }
 }
 
-extern "C" int mpx_plan_destroy(mpx_plan p) {
-    if (!p) return MPX_OK;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->dev) (void)hipFree(p->dev);
-    delete p;
-    return MPX_OK;
-}
+
 
 static int roots_check(mpx_plan p, const void* cre, const void* cim, int64_t psc, void* rre,
                        void* rim, int64_t psr) {
@@ -1468,6 +1638,8 @@ extern "C" int mpx_polyroots(mpx_plan p, const void* coef_re, const void* coef_i
 }
 
 extern "C" int mpx_polyroots_variant_count(void) { return kDkVariantCount; }
+
+extern "C" int mpx_polyroots_get_variant(mpx_plan p) { return p ? p->variant : MPX_EINVAL; }
 
 extern "C" int mpx_polyroots_set_variant(mpx_plan p, int variant) {
     if (!p || variant < 0 || variant >= kDkVariantCount) return MPX_EINVAL;
@@ -1535,6 +1707,7 @@ extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const voi
     const int cur = p->variant;
     const int keep = t[best] < 0.97f * t[cur] ? best : cur;
     p->variant = keep;
+    tune_store(dk_tune_key(p), std::to_string(keep));
     if (best_ms) *best_ms = t[keep];
     return keep;
 }

@@ -90,11 +90,14 @@ def _declare(L):
     sig("mpx_polyval_estrin", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyval_cplx", _i, _i, _l, _l, _v, _l, _v, _v, _l, _v, _v, _l, _i, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
-    sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _i, C.c_uint32)
+    sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _v, _v, _i, C.c_uint32)
+    sig("mpx_gemm_selected_variant", _i, _i, _i, _i, _l, _l, _l)
+    sig("mpx_tune_reload", _i)
     sig("mpx_polyroots", _i, _v, _v, _v, _l, _v, _v, _l, _v, _v)
     sig("mpx_plan_destroy", _i, _v)
     sig("mpx_polyroots_variant_count", _i)
     sig("mpx_polyroots_set_variant", _i, _v, _i)
+    sig("mpx_polyroots_get_variant", _i, _v)
     sig("mpx_polyroots_autotune", _i, _v, _v, _v, _l, _v, _v, _l, _i, C.POINTER(C.c_float), _v)
     for name, res, args in _EXTRA_SIGS:
         if hasattr(L, name):
@@ -537,23 +540,40 @@ DK_INIT, DK_GRAPH = 1, 2
 class RootsPlan:
     """Plan for the batched Durand-Kerner solver (owns its device buffers).
 
-    degrees: host sequence of polynomial degrees (>= 1).  Coefficient columns
-    are packed: polynomial b occupies columns coef_off[b] .. coef_off[b] +
-    deg[b] of (K, total_coef) planes; roots likewise with (K, total_roots)."""
+    degrees: host sequence of polynomial degrees (>= 1).  By default the
+    coefficient columns are packed: polynomial b occupies columns coef_off[b]
+    .. coef_off[b] + deg[b] of (K, total_coef) planes, coef_off the prefix
+    sums of deg + 1; roots likewise with (K, total_roots) and prefix sums of
+    deg.  coef_off / root_off (host sequences of batch + 1 int64 offsets)
+    place the polynomials elsewhere; the planes then need coef_off[-1] and
+    root_off[-1] columns."""
 
-    def __init__(self, p, degrees, iters=200, init=True, graph=True):
+    def __init__(self, p, degrees, iters=200, init=True, graph=True, coef_off=None, root_off=None):
         import numpy as np
         self.p = prec_of(p)
         if self.p == FF:
             raise ValueError("polyroots supports DD / TD / QD")
         self.K = ncomp(self.p)
         self.degrees = np.ascontiguousarray(degrees, dtype=np.int32)
-        self.total_coef = int((self.degrees.astype(np.int64) + 1).sum())
-        self.total_roots = int(self.degrees.astype(np.int64).sum())
+        if (coef_off is None) != (root_off is None):
+            raise ValueError("give both coef_off and root_off, or neither")
+        offs = [None, None]
+        if coef_off is not None:
+            offs = [np.ascontiguousarray(o, dtype=np.int64) for o in (coef_off, root_off)]
+            for o, name in zip(offs, ("coef_off", "root_off")):
+                if o.shape != (self.degrees.size + 1,):
+                    raise ValueError(f"{name}: expected {self.degrees.size + 1} offsets")
+            self.total_coef, self.total_roots = int(offs[0][-1]), int(offs[1][-1])
+        else:
+            self.total_coef = int((self.degrees.astype(np.int64) + 1).sum())
+            self.total_roots = int(self.degrees.astype(np.int64).sum())
+        self.coef_off, self.root_off = offs
         flags = (DK_INIT if init else 0) | (DK_GRAPH if graph else 0)
         h = C.c_void_p()
+        ptr = lambda o: None if o is None else o.ctypes.data_as(C.c_void_p)
         _check(lib().mpx_polyroots_plan(C.byref(h), self.p, self.degrees.size,
-                                        self.degrees.ctypes.data_as(C.c_void_p), int(iters), flags),
+                                        self.degrees.ctypes.data_as(C.c_void_p), ptr(offs[0]), ptr(offs[1]),
+                                        int(iters), flags),
                "mpx_polyroots_plan")
         self._h = h
 
@@ -587,6 +607,9 @@ class RootsPlan:
 
     def set_variant(self, v):
         _check(lib().mpx_polyroots_set_variant(self._h, int(v)), "mpx_polyroots_set_variant")
+
+    def variant(self):
+        return int(lib().mpx_polyroots_get_variant(self._h))
 
     def autotune(self, coef_re, coef_im, roots_re, roots_im, iters_probe=2):
         self._args(coef_re, coef_im, roots_re, roots_im)

@@ -116,6 +116,63 @@ def test_dk_degree_512_200_sweeps_bit_exact():
     assert np.array_equal(to_np(st), wst)
 
 
+def _spread(planes, off_packed, off_new, deg, extra):
+    """Copy packed columns of each polynomial to new offsets; gaps hold NaN."""
+    K = planes.shape[0]
+    out = np.full((K, int(off_new[-1])), np.nan)
+    for b, n in enumerate(deg):
+        w = int(n) + extra
+        out[:, off_new[b]:off_new[b] + w] = planes[:, off_packed[b]:off_packed[b] + w]
+    return out
+
+
+def test_dk_caller_offsets_with_gaps_every_variant():
+    """Polynomials placed at caller-given offsets with NaN-filled gaps between
+    them: every variant reproduces the oracle's sweeps on the packed layout,
+    never reads a gap (a NaN would spread) and never writes one; with the
+    Aberth start the result equals the packed-layout plan's bit for bit."""
+    K = 4
+    deg, cre, cim = _dk_inputs(K, [17, 64, 5, 130, 40, 65, 1], 95)
+    z0r, z0i, _ = oracle.polyroots(K, deg, cre, cim, iters=0, init=True)
+    wr, wi, wst = oracle.polyroots(K, deg, cre, cim, z0r, z0i, iters=4, init=False)
+    cp, rp = synth.offsets(deg)
+    idx = np.arange(deg.size + 1)
+    co, ro = cp + 7 * idx + 2, rp + 3 * idx + 1
+    Cr, Ci = _spread(cre, cp, co, deg, 1), _spread(cim, cp, co, deg, 1)
+    Zr, Zi = _spread(z0r, rp, ro, deg, 0), _spread(z0i, rp, ro, deg, 0)
+    gC_r, gC_i = to_gpu(Cr), to_gpu(Ci)
+    for v in range(mpx.polyroots_variant_count()):
+        plan = mpx.RootsPlan("qd", deg, iters=4, init=False, graph=False, coef_off=co, root_off=ro)
+        plan.set_variant(v)
+        zr, zi = to_gpu(Zr), to_gpu(Zi)
+        st = plan.run(gC_r, gC_i, zr, zi)
+        gr, gi = to_np(zr), to_np(zi)
+        assert bits_equal(gr, _spread(wr, rp, ro, deg, 0)), v   # gaps still NaN
+        assert bits_equal(gi, _spread(wi, rp, ro, deg, 0)), v
+        assert np.array_equal(to_np(st), wst), v
+    # Aberth start values computed on the GPU: same bits in either layout
+    packed = mpx.RootsPlan("qd", deg, iters=3, init=True, graph=False)
+    zr, zi = torch.zeros((K, int(rp[-1])), dtype=torch.float64, device="cuda"), None
+    zi = torch.zeros_like(zr)
+    packed.run(to_gpu(cre), to_gpu(cim), zr, zi)
+    spread = mpx.RootsPlan("qd", deg, iters=3, init=True, graph=False, coef_off=co, root_off=ro)
+    zr2, zi2 = to_gpu(np.full((K, int(ro[-1])), np.nan)), to_gpu(np.full((K, int(ro[-1])), np.nan))
+    spread.run(gC_r, gC_i, zr2, zi2)
+    assert bits_equal(to_np(zr2), _spread(to_np(zr), rp, ro, deg, 0))
+    assert bits_equal(to_np(zi2), _spread(to_np(zi), rp, ro, deg, 0))
+
+
+def test_dk_offsets_rejected():
+    bad = [([0, 3, 6], [0, 3, 6]),      # polynomial 0 of degree 3 needs 4 coefficient columns
+           ([0, 4, 8], [0, 2, 5]),      # and 3 root columns
+           ([-1, 4, 8], [0, 3, 6])]     # negative first offset
+    for co, ro in bad:
+        with pytest.raises(mpx.MpxError):
+            mpx.RootsPlan("qd", [3, 3], iters=1, init=False, graph=False, coef_off=co, root_off=ro)
+    with pytest.raises(ValueError):
+        mpx.RootsPlan("qd", [3, 3], iters=1, coef_off=[0, 4, 8])
+
+
 def test_dk_odd_and_even_iteration_counts_and_resume():
     K = 4
     deg, cre, cim = _dk_inputs(K, [7, 33, 2, 64], 20)

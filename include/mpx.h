@@ -141,6 +141,19 @@ size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k, int
 int mpx_dot(int prec, int64_t n, const void *x, int64_t psx, const void *y, int64_t psy,
             void *result, void *ws, size_t ws_bytes, void *stream);
 
+/* mpx_dot without a workspace, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and result bits as mpx_dot, with the ticket and block
+ * partials in a static device array of the library (33024 bytes per GPU,
+ * enough for every n: the dot never has more than 1024 partials; a larger
+ * need would return MPX_EWORKSPACE).  No allocation of any kind.  Every call
+ * on one GPU shares that array, so calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller.  The array needs no clearing: each call tags the ticket with
+ * its own generation.  The stream must belong to the current device. */
+int mpx_dot_noalloc(int prec, int64_t n, const void *x, int64_t psx, const void *y, int64_t psy,
+                    void *result, void *stream);
+
 /* y = op(A) x, the matrix-vector product of the same basic linear layer
  * (Sections 1 and 3; no separate definition in the paper, so the plain sums
  * are the definition).  A is an m x n row-major matrix with leading

@@ -15,6 +15,7 @@
 #include "mpx_internal.hpp"
 
 #include <atomic>
+#include <mutex>
 
 namespace mpx {
 
@@ -472,6 +473,55 @@ extern "C" int mpx_dot(int prec, int64_t n, const void* x, int64_t psx, const vo
     if (overlaps(result, rb, x, xb) || overlaps(result, rb, y, yb) || overlaps(ws, need, x, xb) ||
         overlaps(ws, need, y, yb) || overlaps(ws, need, result, rb))
         return MPX_EINVAL;
+    MPX_DISPATCH_AR(prec, launch_dot, n, x, psx, y, psy, result, ws, as_stream(stream));
+}
+
+// ------------------------------------------------- allocation-free dot ----
+//
+// mpx_dot_noalloc keeps the multi-block dot's ticket and partials in this
+// file-scope array instead of a caller workspace: the ticket word and up to
+// 1024 partials of up to four binary64 components (every multi-block dot
+// fits), 33024 bytes held by each GPU the library runs on until the process
+// ends.  Host code never uses the array's name as an address: the per-device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+constexpr size_t kDotScratchBytes = kDotTicketBytes + 4 * sizeof(double) * 1024;
+static __device__ __align__(256) unsigned char scratch[kDotScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+static int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MPX_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return MPX_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return MPX_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPX_OK;
+}
+
+extern "C" int mpx_dot_noalloc(int prec, int64_t n, const void* x, int64_t psx, const void* y,
+                               int64_t psy, void* result, void* stream) {
+    int st;
+    if ((st = check_vec(prec, n, x, psx)) || (st = check_vec(prec, n, y, psy))) return st;
+    if (result == nullptr) return MPX_EINVAL;
+    const size_t need = dot_workspace(prec, n);
+    if (need > kDotScratchBytes) return MPX_EWORKSPACE;  // larger than the static scratch
+    const int K = prec_k_ar(prec);
+    const size_t elt = is_ff(base_prec(prec)) ? sizeof(float) : sizeof(double);
+    const uint64_t xb = planes_bytes(K, 1, n, n, psx, elt), yb = planes_bytes(K, 1, n, n, psy, elt);
+    const uint64_t rb = (uint64_t)K * elt;
+    if (overlaps(result, rb, x, xb) || overlaps(result, rb, y, yb)) return MPX_EINVAL;
+    void* ws = nullptr;
+    if (need > 0 && (st = scratch_address(&ws)) != MPX_OK) return st;
     MPX_DISPATCH_AR(prec, launch_dot, n, x, psx, y, psy, result, ws, as_stream(stream));
 }
 

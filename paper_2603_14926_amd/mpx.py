@@ -91,6 +91,7 @@ def _declare(L):
     sig("mpx_polyval_cplx", _i, _i, _l, _l, _v, _l, _v, _v, _l, _v, _v, _l, _i, _v)
     sig("mpx_polyval_backward", _i, _i, _l, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_polyroots_plan", _i, C.POINTER(_v), _i, _l, _v, _v, _v, _i, C.c_uint32)
+    sig("mpx_dot_noalloc", _i, _i, _l, _v, _l, _v, _l, _v, _v)
     sig("mpx_gemm_selected_variant", _i, _i, _i, _i, _l, _l, _l)
     sig("mpx_tune_reload", _i)
     sig("mpx_polyroots", _i, _v, _v, _v, _l, _v, _v, _l, _v, _v)

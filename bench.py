@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--n", type=int, default=2048, help="headline GEMM size (and --only gemm's)")
     ap.add_argument("--prec", default="qd")
     ap.add_argument("--quick", action="store_true", help="headline only (no rows, no CPU baseline)")
     ap.add_argument("--no-8192", action="store_true", help="skip the n = 8192 Ozaki comparison")
@@ -755,7 +755,7 @@ def main():
                           "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE}}), flush=True)
         return
     if args.only:
-        fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, 2048) for q in ("qd", "td", "dd", "ff")},
+        fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, args.n) for q in ("qd", "td", "dd", "ff")},
               "gemv": lambda: gemv_rows(mpx, torch, T),
               "vector": lambda: vector_rows(mpx, torch, T),
               "vector_sweep": lambda: vector_sweep_rows(mpx, torch, T),

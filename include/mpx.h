@@ -132,25 +132,23 @@ size_t mpx_workspace_size(int op, int prec, int64_t m, int64_t n, int64_t k, int
  * separate inner-product routine, so the plain sum is the definition).
  * Per-thread partial sums are sequential BF multiply-adds; partials are
  * combined with BF additions in a fixed tree.  Error <= n * 2^-b *
- * sum |x_i y_i| with b = 104 / 155 / 208 (FF: 46).  One launch: the block
- * that finishes last (an integer ticket in the workspace) adds the block
- * partials.  ws: device workspace of at least mpx_workspace_size(MPX_OP_DOT,
- * prec, n, 0, 0, 0) bytes (0 for n <= 256); its contents need no
- * initialisation (every call tags the ticket with its own generation), but
- * calls that share one workspace must not overlap in time. */
+ * sum |x_i y_i| with b = 104 / 155 / 208 (FF: 46).  ws: device workspace of
+ * at least mpx_workspace_size(MPX_OP_DOT, prec, n, 0, 0, 0) bytes (0 for
+ * n <= 256: one block, one launch; beyond, the block partials and a second
+ * one-block launch that adds them). */
 int mpx_dot(int prec, int64_t n, const void *x, int64_t psx, const void *y, int64_t psy,
             void *result, void *ws, size_t ws_bytes, void *stream);
 
 /* mpx_dot without a workspace, for callers that cannot allocate (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
- * the same kernels and result bits as mpx_dot, with the ticket and block
- * partials in a static device array of the library (33024 bytes per GPU,
- * enough for every n: the dot never has more than 1024 partials; a larger
- * need would return MPX_EWORKSPACE).  No allocation of any kind.  Every call
- * on one GPU shares that array, so calls that overlap in time on one GPU (on
- * different streams, or from different threads) race and must be ordered by
- * the caller.  The array needs no clearing: each call tags the ticket with
- * its own generation.  The stream must belong to the current device. */
+ * the same kernels and result bits as mpx_dot, with the block partials in
+ * a static device array of the library (32 KiB per GPU, enough for every n:
+ * the dot never has more than 1024 partials; a larger need would return
+ * MPX_EWORKSPACE).  No allocation of any kind.  Every call on one GPU shares
+ * that array, so calls that overlap in time on one GPU (on different
+ * streams, or from different threads) race and must be ordered by the
+ * caller.  The array needs no clearing (each call writes every partial it
+ * reads).  The stream must belong to the current device. */
 int mpx_dot_noalloc(int prec, int64_t n, const void *x, int64_t psx, const void *y, int64_t psy,
                     void *result, void *stream);
 
@@ -413,8 +411,8 @@ int mpx_plan_destroy(mpx_plan plan);
  * a lane-packed schedule: 4-, 8- or 12-wave jobs whose roots are laid out
  * lane by lane over 64-lane items, so roots of several polynomials share a
  * wave and small polynomials fill lanes a larger one leaves idle); results
- * do not depend on the variant.  A new plan uses the packed schedule with 8
- * resident waves per CU, or the variant the tune cache holds for its
+ * do not depend on the variant.  A new plan uses lane-packed 12-wave jobs
+ * (one per CU), or the variant the tune cache holds for its
  * (precision, batch, largest degree) bucket, or MPX_DK_VARIANT (see the GEMM
  * tuning notes).  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants

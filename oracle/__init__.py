@@ -33,6 +33,11 @@ _vp = C.c_void_p
 
 
 def _load(name):
+    # MPX_ORACLE_LIBRARY names another build of liboracle.so (the CPU tests
+    # run the oracle's pins against an AddressSanitizer build this way)
+    alt = os.environ.get("MPX_ORACLE_LIBRARY")
+    if alt and name == "liboracle.so":
+        return C.CDLL(alt)
     path = os.path.join(_HERE, name)
     if not os.path.exists(path):
         from . import build as _b  # noqa: WPS433  (oracle's own build step)

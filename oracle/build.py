@@ -31,5 +31,14 @@ def build(verbose: bool = False) -> None:
         os.replace(out + ".tmp", out)
 
 
+def build_asan(out: str) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (for
+    the CPU tests; load it with libasan preloaded)."""
+    cmd = ["gcc", *FLAGS, "-fopenmp", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-g", SRC, "-o", out, "-lm"]
+    subprocess.check_call(cmd)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)

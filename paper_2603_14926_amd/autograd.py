@@ -9,6 +9,17 @@ the Horner recurrence, x gradient by the derivative recurrence).
 
 Gradients are multicomponent tensors of the same layout; autograd only routes
 them (no torch arithmetic touches the components).
+
+Cotangent convention: the gradient arriving at a multicomponent output is
+read as ONE multicomponent number per entry, the unevaluated sum of its K
+planes, and the gradients returned for the inputs have the same form.
+Torch's own operations do not follow it: composing a multicomponent output
+with a plain torch reduction, e.g. gemm(A, B).sum(), hands every plane a
+gradient of 1, i.e. the number K, so the input gradients come out K times
+too large in plane 0.  Route such losses through to_value(), whose backward
+hands the incoming binary64 gradient on as (g, 0, ..., 0):
+    to_value(gemm(A, B)).sum().backward()
+gives the gradients of the sum of the entries' values.
 """
 from __future__ import annotations
 
@@ -58,3 +69,26 @@ def gemm(A, B, prec="qd"):
 
 def polyval(coef, x, prec="qd"):
     return MpPolyval.apply(coef, x, prec)
+
+
+class MpValue(torch.autograd.Function):
+    """Multicomponent planes (K, ...) -> their leading components (...), the
+    values to binary64 precision (no arithmetic: a copy of plane 0).  Its
+    backward turns a plain gradient g into the multicomponent cotangent
+    (g, 0, ..., 0)."""
+
+    @staticmethod
+    def forward(ctx, x):
+        ctx.K = x.shape[0]
+        return x[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        out = torch.zeros((ctx.K,) + tuple(g.shape), dtype=g.dtype, device=g.device)
+        out[0] = g
+        return out
+
+
+def to_value(x):
+    return MpValue.apply(x)
+

@@ -14,7 +14,6 @@
 #include "mp_conv.hpp"
 #include "mpx_internal.hpp"
 
-#include <atomic>
 #include <mutex>
 
 namespace mpx {
@@ -148,61 +147,16 @@ k_dot_partial(long long n, const T* __restrict__ x, long long psx, const T* __re
     if (threadIdx.x == 0) mp_store<T, K>(out, pso, blockIdx.x, acc);
 }
 
-// Ticket of the single-launch dot: one 64-bit word, (generation << 32) |
-// blocks done.  The host gives every call its own generation; a block finding
-// another generation in the word (a fresh workspace, or another call's) starts
-// the count afresh, so the word needs no clearing.  The last block leaves
-// (generation, 0), so replays of a captured call (same generation) start from
-// zero as well.  Returns how many blocks of this call came before.
-__device__ __forceinline__ unsigned dot_ticket(unsigned long long* t, unsigned gen) {
-    unsigned long long old = __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {  // ends: a failed exchange means another block's succeeded
-        const bool mine = (unsigned)(old >> 32) == gen;
-        const unsigned long long want = mine ? old + 1 : (((unsigned long long)gen << 32) | 1ULL);
-        const unsigned long long seen = atomicCAS(t, old, want);
-        if (seen == old) return mine ? (unsigned)(old & 0xffffffffULL) : 0u;
-        old = seen;
-    }
-}
-
-// Single-launch dot: stage 1 as k_dot_partial into part[b]; the block that
-// takes the last ticket then adds the gridDim.x partials exactly as a
-// separate one-block pass would (thread-sequential, then the block tree), so
-// the rounding is that of the two-pass form, in one launch.
+// Stage 2: one block adds the nparts partials (thread-sequential, then the
+// block tree) into K contiguous values.
 template <typename T, int K, int AR>
 __global__ void __launch_bounds__(kBlock)
-k_dot_fused(long long n, const T* __restrict__ x, long long psx, const T* __restrict__ y,
-            long long psy, T* part, long long psp, unsigned long long* ticket, unsigned gen,
-            T* __restrict__ out) {
-    const long long stride = (long long)gridDim.x * kBlock;
+k_sum_parts(long long nparts, const T* __restrict__ part, long long psp, T* __restrict__ out) {
     mpn<T, K> acc = mp_zero<T, K>();
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        acc = ar_add<AR>(acc, ar_mul<AR>(mp_load_stream<T, K>(x, psx, i),
-                                         mp_load_stream<T, K>(y, psy, i)));
+    for (long long i = threadIdx.x; i < nparts; i += kBlock)
+        acc = ar_add<AR>(acc, mp_load<T, K>(part, psp, i));
     acc = block_sum<T, K, AR>(acc);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        mp_store<T, K>(part, psp, blockIdx.x, acc);
-        __threadfence();  // the partial is visible device-wide before the ticket
-        s_last = dot_ticket(ticket, gen) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;  // uniform in the block
-    __threadfence();      // every partial written before its block's ticket is seen
-    acc = mp_zero<T, K>();
-    for (long long i = threadIdx.x; i < gridDim.x; i += kBlock) {
-        mpn<T, K> v;
-#pragma unroll
-        for (int c = 0; c < K; ++c)
-            v.c[c] = __hip_atomic_load(&part[c * psp + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        acc = ar_add<AR>(acc, v);
-    }
-    acc = block_sum<T, K, AR>(acc);
-    if (threadIdx.x == 0) {
-        mp_store<T, K>(out, 1, 0, acc);
-        __hip_atomic_store(ticket, (unsigned long long)gen << 32, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) mp_store<T, K>(out, 1, 0, acc);
 }
 
 // Number of stage-1 blocks: a function of n alone (the summation tree, and so
@@ -217,12 +171,6 @@ static long long dot_blocks(long long n) {
     return b > 1024 ? 1024 : b;  // 1024 partials stream faster than 2048 or more
 }
 
-// Workspace layout of a multi-block dot: the ticket word in the first 256
-// bytes, then K planes of nb partials.
-constexpr size_t kDotTicketBytes = 256;
-
-static std::atomic<unsigned> g_dot_gen{1};
-
 template <typename T, int K, int AR>
 static int launch_dot(long long n, const void* x, long long psx, const void* y, long long psy,
                       void* result, void* ws, hipStream_t s) {
@@ -232,10 +180,11 @@ static int launch_dot(long long n, const void* x, long long psx, const void* y, 
                                                   (T*)result, 1);
         return launch_status();
     }
-    const unsigned gen = g_dot_gen.fetch_add(1, std::memory_order_relaxed);
-    k_dot_fused<T, K, AR><<<(int)nb, kBlock, 0, s>>>(
-        n, (const T*)x, psx, (const T*)y, psy, (T*)((char*)ws + kDotTicketBytes), nb,
-        (unsigned long long*)ws, gen, (T*)result);
+    k_dot_partial<T, K, AR><<<(int)nb, kBlock, 0, s>>>(n, (const T*)x, psx, (const T*)y, psy,
+                                                    (T*)ws, nb);
+    int st = launch_status();
+    if (st != MPX_OK) return st;
+    k_sum_parts<T, K, AR><<<1, kBlock, 0, s>>>(nb, (const T*)ws, nb, (T*)result);
     return launch_status();
 }
 
@@ -379,7 +328,7 @@ size_t dot_workspace(int prec, long long n) {
     const long long nb = dot_blocks(n);
     if (nb == 1) return 0;
     const size_t elt = is_ff(base_prec(prec)) ? sizeof(float) : sizeof(double);
-    return kDotTicketBytes + elt * (size_t)prec_k_ar(prec) * (size_t)nb;
+    return elt * (size_t)prec_k_ar(prec) * (size_t)nb;
 }
 
 }  // namespace mpx
@@ -478,14 +427,15 @@ extern "C" int mpx_dot(int prec, int64_t n, const void* x, int64_t psx, const vo
 
 // ------------------------------------------------- allocation-free dot ----
 //
-// mpx_dot_noalloc keeps the multi-block dot's ticket and partials in this
-// file-scope array instead of a caller workspace: the ticket word and up to
-// 1024 partials of up to four binary64 components (every multi-block dot
-// fits), 33024 bytes held by each GPU the library runs on until the process
-// ends.  Host code never uses the array's name as an address: the per-device
-// address comes from hipGetSymbolAddress, taken once per device with that
-// device current.
-constexpr size_t kDotScratchBytes = kDotTicketBytes + 4 * sizeof(double) * 1024;
+// mpx_dot_noalloc keeps the multi-block dot's block partials in this
+// file-scope array instead of a caller workspace: up to 1024 partials of up
+// to four binary64 components (every multi-block dot fits), 32 KiB held by
+// each GPU the library runs on until the process ends.  Every partial is
+// written by the first kernel before the second reads it, so nothing needs
+// clearing.  Host code never uses the array's name as an address: the
+// per-device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+constexpr size_t kDotScratchBytes = 4 * sizeof(double) * 1024;
 static __device__ __align__(256) unsigned char scratch[kDotScratchBytes];
 
 constexpr int kMaxDevices = 64;

@@ -16,7 +16,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmpx.so")
+# MPX_LIBRARY names another build of the library (the CPU tests load an
+# AddressSanitizer build of the host code this way).
+LIB_PATH = os.environ.get("MPX_LIBRARY") or os.path.join(_HERE, "libmpx.so")
 
 DD, TD, QD, FF = 2, 3, 4, 0x102
 # Arithmetic flags OR-ed into DD / TD / QD: the conventional (non-branch-free)

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2603_14926_amd import mpx
@@ -197,3 +199,58 @@ def test_polynomial_outputs_overlapping_inputs_rejected():
     assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, gc, 32, in_x, 8, None) == -1
     assert L.mpx_polyval_backward(4, 8, 3, coef, 32, x, 8, gy, 8, gc, 32,
                                   C.c_void_p(base + (6 << 20) + 8), 8, None) == -1           # gx in gcoef
+
+
+def _plan_ok_or_no_device(r):
+    """A valid plan is built (0) when a GPU is present; without one the
+    schedule is still built on the host and the first device allocation fails
+    (MPX_EDEVICE)."""
+    return r in (0, -5)
+
+
+def test_roots_plan_host_schedules():
+    """The plan constructor's host work (validation, LPT order, packed and
+    lane-packed schedules) on ragged batches, with packed and caller offsets;
+    run under AddressSanitizer by test_asan_host.py."""
+    L = mpx.lib()
+    rng = np.random.default_rng(3)
+    for degs in ([1], [64, 1, 65, 128, 3], rng.integers(1, 600, 500).tolist(), [512] * 40 + [16] * 300):
+        d = np.ascontiguousarray(degs, np.int32)
+        for offs in (False, True):
+            co = ro = None
+            if offs:
+                co = np.concatenate([[5], 5 + np.cumsum(d.astype(np.int64) + 3)]).astype(np.int64)
+                ro = np.concatenate([[0], np.cumsum(d.astype(np.int64) + 1)]).astype(np.int64)
+            h = C.c_void_p()
+            r = L.mpx_polyroots_plan(C.byref(h), 4, d.size, d.ctypes.data_as(C.c_void_p),
+                                     None if co is None else co.ctypes.data_as(C.c_void_p),
+                                     None if ro is None else ro.ctypes.data_as(C.c_void_p), 3, 0)
+            assert _plan_ok_or_no_device(r), r
+            if r == 0:
+                assert L.mpx_plan_destroy(h) == 0
+    d = np.array([3, 0], np.int32)
+    h = C.c_void_p()
+    assert L.mpx_polyroots_plan(C.byref(h), 4, 2, d.ctypes.data_as(C.c_void_p), None, None, 1, 0) == -1
+    d = np.array([3, 3], np.int32)
+    co = np.array([0, 3, 8], np.int64)        # polynomial 0 needs 4 coefficient columns
+    ro = np.array([0, 3, 6], np.int64)
+    assert L.mpx_polyroots_plan(C.byref(h), 4, 2, d.ctypes.data_as(C.c_void_p),
+                                co.ctypes.data_as(C.c_void_p), ro.ctypes.data_as(C.c_void_p), 1, 0) == -1
+    assert L.mpx_polyroots_plan(C.byref(h), 4, 2, d.ctypes.data_as(C.c_void_p),
+                                co.ctypes.data_as(C.c_void_p), None, 1, 0) == -1      # only one given
+    assert L.mpx_polyroots_plan(C.byref(h), 4, 2, d.ctypes.data_as(C.c_void_p), None, None, 1, 4) == -1
+
+
+def test_batched_gemm_plan_host_schedule():
+    L = mpx.lib()
+    rng = np.random.default_rng(4)
+    for cnt in (1, 7, 300):
+        ms = np.ascontiguousarray(rng.integers(0, 130, cnt), np.int64)
+        ns = np.ascontiguousarray(rng.integers(1, 130, cnt), np.int64)
+        ks = np.ascontiguousarray(rng.integers(0, 130, cnt), np.int64)
+        h = C.c_void_p()
+        r = L.mpx_gemm_batched_plan(C.byref(h), 4, cnt, ms.ctypes.data_as(C.c_void_p),
+                                    ns.ctypes.data_as(C.c_void_p), ks.ctypes.data_as(C.c_void_p))
+        assert _plan_ok_or_no_device(r), r
+        if r == 0:
+            assert L.mpx_gemm_plan_destroy(h) == 0

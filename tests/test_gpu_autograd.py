@@ -158,3 +158,27 @@ def test_polyval_x_gradient_finite_differences_and_exact_derivative():
         terms = [i * exact.value(coef[:, b, i]) * xv ** (i - 1) for i in range(1, deg + 1)]
         d = sum(terms)
         assert abs(got - d) <= Fraction(2.0 ** -200) * (1 + sum(abs(t) for t in terms)), b
+
+
+@pytest.mark.parametrize("p,K", [("qd", 4), ("dd", 2)])
+def test_plain_torch_loss_through_to_value(p, K):
+    """A loss built from plain torch operations reaches the multicomponent
+    backward through to_value(): the cotangent is (1, 0, ..., 0) per entry,
+    so A.grad = ones B^T and B.grad = A^T ones, bit for bit; summing the raw
+    planes instead hands in the number K (the documented convention)."""
+    m, n, k = 19, 23, 31
+    A = synth.mp_array(K, (m, k), 41, "U")
+    B = synth.mp_array(K, (k, n), 42, "U")
+    ones = np.zeros((K, m, n)); ones[0] = 1.0
+    Bt = np.ascontiguousarray(B.transpose(0, 2, 1))
+    At = np.ascontiguousarray(A.transpose(0, 2, 1))
+    tA = to_gpu(A).requires_grad_(True)
+    tB = to_gpu(B).requires_grad_(True)
+    ag.to_value(ag.gemm(tA, tB, p)).sum().backward()
+    assert bits_equal(to_np(tA.grad), oracle.gemm(K, ones, Bt))
+    assert bits_equal(to_np(tB.grad), oracle.gemm(K, At, ones))
+    tA2 = to_gpu(A).requires_grad_(True)
+    ag.gemm(tA2, to_gpu(B), p).sum().backward()
+    # every plane's gradient 1 is read as one multicomponent cotangent, the number K
+    assert bits_equal(to_np(tA2.grad), oracle.gemm(K, np.ones((K, m, n)), Bt))
+    assert np.allclose(to_np(tA2.grad)[0], K * to_np(tA.grad)[0], rtol=1e-12, atol=0)

@@ -750,7 +750,9 @@ def main():
     mpx.lib()
     T = Timer(torch)
     if args.peak_probe:
-        r = {k: mpx.probe_valu(k) for k in mpx.PROBES}
+        # launches of ~60 ms (2^16 iterations), the engine clock brought to its
+        # steady state by 10 untimed launches, median of 5
+        r = {k: mpx.probe_valu(k, iters=1 << 16, reps=5, warmup=10) for k in mpx.PROBES}
         print(json.dumps({"peak_probe_lane_ops_per_s": r,
                           "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE}}), flush=True)
         return

@@ -49,7 +49,7 @@ constexpr int kGemmThreads = 256;
 // One BM x BN tile of C = op(A) op(B) at (m0, n0), computed by the 256
 // threads of a workgroup with the LDS panels sA, sB (shared by k_gemm and the
 // batched kernel, so both give the same bits).
-template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR>
+template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR, bool PF = false>
 __device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restrict__ A,
                                           long long lda, long long psA, const T* __restrict__ B,
                                           long long ldb, long long psB, T* __restrict__ C,
@@ -116,8 +116,7 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restri
             }
         }
     };
-    auto mac_step = [&](int kk) {
-        mpn<T, K> a[TM], b[TN];
+    auto load_ab = [&](int kk, mpn<T, K> (&a)[TM], mpn<T, K> (&b)[TN]) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -126,10 +125,38 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restri
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int c = 0; c < K; ++c) b[j].c[c] = sB[c][kk][tx + 16 * j];
+    };
+    auto mac_ab = [&](const mpn<T, K> (&a)[TM], const mpn<T, K> (&b)[TN]) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[i][j] = ar_add<AR>(acc[i][j], ar_mul<AR>(a[i], b[j]));
+    };
+    auto mac_step = [&](int kk) {
+        mpn<T, K> a[TM], b[TN];
+        load_ab(kk, a, b);
+        mac_ab(a, b);
+    };
+    // PF: a full panel with the LDS operands of step kk + 1 read before the
+    // arithmetic of step kk (the scheduling barrier keeps them there), so the
+    // LDS latency overlaps a whole multiply-add; for short multiply-adds on
+    // small tiles.  Same operations in the same order.
+    auto panel_pf = [&]() {
+        mpn<T, K> a[TM], b[TN];
+        load_ab(0, a, b);
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            mpn<T, K> an[TM], bn[TN];
+            if (kk + 1 < BK) load_ab(kk + 1, an, bn);
+            __builtin_amdgcn_sched_barrier(0);
+            mac_ab(a, b);
+            if (kk + 1 < BK) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) a[i] = an[i];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[j] = bn[j];
+            }
+        }
     };
 
     if (k > 0) fetch(0);
@@ -140,8 +167,12 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restri
         if (k0 + BK < k) fetch(k0 + BK);  // overlaps the MACs below
         const int kend = k - k0;
         if (kend >= BK) {
+            if constexpr (PF) {
+                panel_pf();
+            } else {
 #pragma unroll
-            for (int kk = 0; kk < BK; ++kk) mac_step(kk);
+                for (int kk = 0; kk < BK; ++kk) mac_step(kk);
+            }
         } else {
             for (int kk = 0; kk < kend; ++kk) mac_step(kk);
         }
@@ -160,7 +191,7 @@ __device__ __forceinline__ void gemm_tile(int m, int n, int k, const T* __restri
 }
 
 
-template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR>
+template <typename T, int K, int TM, int TN, int BK, bool TA, bool TB, int AR, bool PF = false>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
        const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
@@ -188,8 +219,8 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
     const int m0 = (first_m + r % rows_here) * BM;
     const int n0 = (r / rows_here) * BN;
 
-    gemm_tile<T, K, TM, TN, BK, TA, TB, AR>(m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC, m0,
-                                            n0, sA, sB);
+    gemm_tile<T, K, TM, TN, BK, TA, TB, AR, PF>(m, n, k, A, lda, psA, B, ldb, psB, C, ldc, psC, m0,
+                                                n0, sA, sB);
 }
 
 // ----------------------------------------------------------- variants ----
@@ -201,7 +232,7 @@ struct GemmArgs {
     void* C; long long ldc, psC;
 };
 
-template <typename T, int K, int TM, int TN, int BK, int AR>
+template <typename T, int K, int TM, int TN, int BK, int AR, bool PF = false>
 static int run_variant(const GemmArgs& g, hipStream_t s) {
     constexpr int BM = 16 * TM, BN = 16 * TN;
     const long long tiles = ceil_div(g.n, BN) * ceil_div(g.m, BM);
@@ -210,7 +241,7 @@ static int run_variant(const GemmArgs& g, hipStream_t s) {
     const int total = (int)tiles;
     if (total == 0) return MPX_OK;
 #define MPX_GEMM_LAUNCH(TA_, TB_)                                                           \
-    k_gemm<T, K, TM, TN, BK, TA_, TB_, AR><<<total, kGemmThreads, 0, s>>>(                  \
+    k_gemm<T, K, TM, TN, BK, TA_, TB_, AR, PF><<<total, kGemmThreads, 0, s>>>(              \
         g.m, g.n, g.k, (const T*)g.A, g.lda, g.psA, (const T*)g.B, g.ldb, g.psB, (T*)g.C,   \
         g.ldc, g.psC, tn, total)
     if (!g.tA && !g.tB) MPX_GEMM_LAUNCH(false, false);
@@ -249,15 +280,29 @@ static const std::vector<Variant>& variants(int prec) {
     // leaves one workgroup per CU
     static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd"),
                                             {run_variant<double, 2, 1, 2, 16, AR_BF>, 16, 32, "dd_1x2_k16"},
-                                            {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"}};
+                                            {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"},
+                                            {run_variant<double, 2, 1, 2, 16, AR_BF, true>, 16, 32, "dd_1x2_k16_pf"},
+                                            {run_variant<double, 2, 1, 1, 16, AR_BF, true>, 16, 16, "dd_1x1_k16_pf"},
+                                            {run_variant<double, 2, 2, 2, 16, AR_BF, true>, 32, 32, "dd_2x2_k16_pf"},
+                                            {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
-                                            {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"}};
-    static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
+                                            {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},
+                                            {run_variant<double, 3, 1, 1, 16, AR_BF, true>, 16, 16, "td_1x1_k16_pf"},
+                                            {run_variant<double, 3, 1, 2, 16, AR_BF, true>, 16, 32, "td_1x2_k16_pf"},
+                                            {run_variant<double, 3, 2, 2, 8, AR_BF, true>, 32, 32, "td_2x2_k8_pf"}};
+    static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd"),
+                                            {run_variant<double, 4, 1, 1, 16, AR_BF, true>, 16, 16, "qd_1x1_k16_pf"},
+                                            {run_variant<double, 4, 1, 2, 16, AR_BF, true>, 16, 32, "qd_1x2_k16_pf"},
+                                            {run_variant<double, 4, 2, 2, 8, AR_BF, true>, 32, 32, "qd_2x2_k8_pf"}};
     static const std::vector<Variant> ff = {
         {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},
         {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},
         {run_variant<float, 2, 2, 4, 8, AR_BF>, 32, 64, "ff_2x4_k8"},
         {run_variant<float, 2, 2, 2, 16, AR_BF>, 32, 32, "ff_2x2_k16"},
+        {run_variant<float, 2, 4, 4, 8, AR_BF, true>, 64, 64, "ff_4x4_k8_pf"},
+        {run_variant<float, 2, 2, 4, 8, AR_BF, true>, 32, 64, "ff_2x4_k8_pf"},
+        {run_variant<float, 2, 2, 2, 16, AR_BF, true>, 32, 32, "ff_2x2_k16_pf"},
+        {run_variant<float, 2, 1, 1, 16, AR_BF, true>, 16, 16, "ff_1x1_k16_pf"},
     };
     static const std::vector<Variant> dd_nobf = {MPX_TILES_DD(AR_NOBF, "dd_nobf")};
     static const std::vector<Variant> td_nobf = {MPX_TILES_TD(AR_NOBF, "td_nobf")};
@@ -302,14 +347,18 @@ static int variant_by_name(int prec, const std::string& name) {
 }
 
 // Untuned default: the largest tile that still yields at least 2048
-// workgroups (8 per CU), else the smallest tile.
+// workgroups (8 per CU), else the smallest tile; among equal tiles the first
+// listed.
 static int default_variant(int prec, const GemmArgs& g) {
     const auto& v = variants(prec);
+    int best = -1, smallest = 0;
     for (size_t i = 0; i < v.size(); ++i) {
+        const long long area = (long long)v[i].bm * v[i].bn;
         const long long wg = ceil_div(g.m, v[i].bm) * ceil_div(g.n, v[i].bn);
-        if (wg >= 2048) return (int)i;
+        if (wg >= 2048 && (best < 0 || area > (long long)v[best].bm * v[best].bn)) best = (int)i;
+        if (area < (long long)v[smallest].bm * v[smallest].bn) smallest = (int)i;
     }
-    return (int)v.size() - 1;
+    return best >= 0 ? best : smallest;
 }
 
 // A tiling forced by MPX_GEMM_VARIANT (comma-separated names), else the tuned

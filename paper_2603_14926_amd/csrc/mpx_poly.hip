@@ -970,13 +970,14 @@ struct DkVariant {
 static const DkVariant kDkVariants[] = {
     {1, 8, DK_WAVE, 1, 0, -1},    {2, 8, DK_WAVE, 1, 0, -1},    {1, 16, DK_WAVE, 1, 0, -1},
     {2, 12, DK_WAVE, 1, 0, -1},   {1, 8, DK_PACKED, 4, 0, -1},  {1, 12, DK_PACKED, 4, 0, -1},
-    {1, 8, DK_LANES, 4, 150, 0},  {1, 8, DK_LANES, 8, 150, 1},  {1, 8, DK_LANES, 8, 200, 2},
+    {1, 12, DK_LANES, 4, 100, 0}, {1, 12, DK_LANES, 4, 150, 1}, {1, 8, DK_LANES, 4, 100, 2},
     {1, 12, DK_LANES, 12, 200, 3}};
 constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
 constexpr int kDkLaneScheds = 4;
-// A new plan's variant: lane-packed 12-wave jobs, one per CU (on 4096 QD
-// polynomials of degrees 16..512 over 200 sweeps: 4.02 s, against 4.13 s
-// for the packed 4-wave chunks and 4.04-4.10 s for 4-wave lane-packed jobs).
+// A new plan's variant: lane-packed 12-wave jobs, one per CU.  On 4096 QD
+// polynomials of degrees 16..512 over 200 sweeps it took 4.02-4.04 s in
+// every run, against 4.12-4.14 s for the packed 4-wave chunks; lane-packed
+// 4-wave jobs at three per CU ranged from 3.96 to 4.24 s from run to run.
 constexpr int kDkDefaultVariant = 9;
 
 }  // namespace mpx

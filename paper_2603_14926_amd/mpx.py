@@ -354,20 +354,24 @@ def gemm_strassen(p, A, B, cutoff, out=None, ws=None):
 PROBES = {"f64_add": 0, "f64_fma": 1, "f32_add": 2, "f32_fma": 3}
 
 
-def probe_valu(kind: str, iters: int = 1 << 12, reps: int = 3) -> float:
+def probe_valu(kind: str, iters: int = 1 << 12, reps: int = 3, warmup: int = 1) -> float:
     """Measured VALU issue rate (lane-operations per second) of one
-    instruction kind, from independent chains on 8 workgroups per CU."""
+    instruction kind, from independent chains on 8 workgroups per CU: the
+    median over `reps` launches after `warmup` untimed ones."""
+    import statistics
     k = PROBES[kind]
     threads = int(lib().mpx_probe_threads())
     out = torch.empty(threads, dtype=torch.float64 if k < 2 else torch.float32, device="cuda")
-    _check(lib().mpx_probe_valu(k, iters, _ptr(out), threads, _stream()), "mpx_probe_valu")  # warm-up
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+    for _ in range(warmup):
         _check(lib().mpx_probe_valu(k, iters, _ptr(out), threads, _stream()), "mpx_probe_valu")
-    e1.record()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        _check(lib().mpx_probe_valu(k, iters, _ptr(out), threads, _stream()), "mpx_probe_valu")
+        e1.record()
     torch.cuda.synchronize()
-    return threads * iters * 64.0 * reps / (e0.elapsed_time(e1) * 1e-3)
+    ms = statistics.median(e0.elapsed_time(e1) for e0, e1 in ev)
+    return threads * iters * 64.0 / (ms * 1e-3)
 
 
 class GemmBatchPlan:

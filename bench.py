@@ -15,7 +15,7 @@ measured on its own synthetic workload:
   gemv          n = 8192 (QD, TD, DD);
   vector        AXPY and dot at n = 4096 (latency) and n = 2^24 (HBM);
   cgemm_3m      complex GEMM by the 3M method at n = 2048 and 2049;
-  polyeval      Horner versus Estrin, batch 1024, degrees 16 .. 2047;
+  polyeval      Horner versus Estrin, batch 1024, degrees 16 .. 4095;
   durand_kerner 4096 complex QD polynomials, degrees 16..512, 200 sweeps
                 in one graph-replayed persistent launch: roots/s, residual,
                 error on 16 known-root polynomials;
@@ -306,21 +306,22 @@ def vector_sweep_rows(mpx, torch, T):
 def polyeval_rows(mpx, torch, T):
     """Real-argument polynomial evaluation (Section 4.1): Horner (one thread
     per polynomial, a dependent chain of deg steps) versus Estrin (one wave per
-    polynomial, log-depth), batch 1024, random coefficients, x in [-1, 1)."""
+    polynomial, log-depth; four waves for lists of 2^12 and more), batch 1024,
+    random coefficients, x in [-1, 1)."""
     from paper_2603_14926_amd import synth
     out = {}
     batch = 1024
     for p in ("qd", "td", "dd"):
         K = mpx.ncomp(p)
-        for deg in (16, 64, 256, 1024, 2047):
+        for deg in (16, 64, 256, 1024, 2047, 4095):
             coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
             x = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
             y = torch.empty((K, batch), dtype=torch.float64, device="cuda")
             th = T(lambda: mpx.polyval(p, coef, x, out=y))
             te = T(lambda: mpx.polyval(p, coef, x, out=y, method="estrin"))
             out[f"{p}_deg{deg}"] = {"horner_us": th * 1e3, "estrin_us": te * 1e3, "estrin_speedup": th / te}
-        # the same at complex points (real coefficients; Estrin up to degree 1023)
-        for deg in (16, 64, 256, 1023):
+        # the same at complex points (real coefficients; Estrin up to degree 4095)
+        for deg in (16, 64, 256, 1023, 2047):
             coef = gpu_mp(torch, K, (batch, deg + 1), synth.seed_for(6, deg))
             xr = gpu_mp(torch, K, batch, synth.seed_for(6, 1))
             xi = gpu_mp(torch, K, batch, synth.seed_for(6, 2))

@@ -210,10 +210,11 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
  * m_p x k_p times k_p x n_p in one persistent launch: workgroups pull
  * (problem, tile) items, longest k first, from a counter and run the tile
  * routine of mpx_gemm, so every entry is bit-identical to mpx_gemm's (the
- * naive triple loop's sequence).  The tilings offered: mpx_gemm's, 8 x 8
- * tiles computed by one wave each, and (TD, QD) a mixed tiling with
- * workgroup tiles over each product's interior and wave tiles over its
- * ragged edges.  Operands are packed per component plane:
+ * naive triple loop's sequence).  The tilings offered: mpx_gemm's (some
+ * with the LDS-prefetching panel loop), 8 x 8 tiles computed by one wave
+ * each, and mixed tilings with workgroup tiles over each product's interior
+ * and wave tiles over its ragged edges.  Operands are packed per component
+ * plane:
  * A_p starts at element sum_{q<p} m_q k_q, row-major with ld = k_p; B_p at
  * sum_{q<p} k_q n_q (ld = n_p); C_p at sum_{q<p} m_q n_q (ld = n_p); plane
  * strides psA / psB / psC at least the totals.  The plan (host arrays copied

@@ -513,7 +513,7 @@ struct GbItem {
 
 __global__ void k_gb_reset(int* c) { *c = 0; }
 
-template <typename T, int K, int TM, int TN, int BK, int AR>
+template <typename T, int K, int TM, int TN, int BK, int AR, bool PF = false>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm_batched(int nitems, const GbItem* __restrict__ items, const GbProb* __restrict__ probs,
                const T* __restrict__ A, long long psA, const T* __restrict__ B, long long psB,
@@ -529,9 +529,9 @@ k_gemm_batched(int nitems, const GbItem* __restrict__ items, const GbProb* __res
         if (it >= nitems) break;  // the same value in every thread: uniform exit
         const GbItem w = items[it];
         const GbProb q = probs[w.p];
-        gemm_tile<T, K, TM, TN, BK, false, false, AR>(q.m, q.n, q.k, A + q.a, q.k, psA, B + q.b,
-                                                      q.n, psB, C + q.c, q.n, psC, w.m0, w.n0,
-                                                      sA, sB);
+        gemm_tile<T, K, TM, TN, BK, false, false, AR, PF>(q.m, q.n, q.k, A + q.a, q.k, psA, B + q.b,
+                                                          q.n, psB, C + q.c, q.n, psC, w.m0, w.n0,
+                                                          sA, sB);
     }
 }
 
@@ -598,7 +598,7 @@ k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
 // workgroup tile are reached by every thread.
 constexpr int kGbTileUnit = -2;
 
-template <typename T, int K, int TM, int TN, int BK, int U, int AR>
+template <typename T, int K, int TM, int TN, int BK, int U, int AR, bool PF = false>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm_batched_mixed(int nunits, const GbItem* __restrict__ items,
                      const GbProb* __restrict__ probs, const T* __restrict__ A, long long psA,
@@ -618,9 +618,9 @@ k_gemm_batched_mixed(int nunits, const GbItem* __restrict__ items,
         if (unit[1].p == kGbTileUnit) {
             const GbItem w = unit[0];
             const GbProb q = probs[w.p];
-            gemm_tile<T, K, TM, TN, BK, false, false, AR>(q.m, q.n, q.k, A + q.a, q.k, psA,
-                                                          B + q.b, q.n, psB, C + q.c, q.n, psC,
-                                                          w.m0, w.n0, sA, sB);
+            gemm_tile<T, K, TM, TN, BK, false, false, AR, PF>(q.m, q.n, q.k, A + q.a, q.k, psA,
+                                                              B + q.b, q.n, psB, C + q.c, q.n, psC,
+                                                              w.m0, w.n0, sA, sB);
         } else {
             const GbItem w = unit[wv];
             if (w.p >= 0) wave_tile<T, K, U, AR>(w, probs[w.p], A, psA, B, psB, C, psC);
@@ -636,20 +636,20 @@ struct GbVariant {
     bool mixed;  // work units of the mixed tiling (bm x bn interior, 8 x 8 edges)
 };
 
-template <typename T, int K, int TM, int TN, int BK, int AR>
+template <typename T, int K, int TM, int TN, int BK, int AR, bool PF = false>
 static int gb_launch(int nitems, const GbItem* items, const GbProb* probs, const void* A,
                      long long psA, const void* B, long long psB, void* C, long long psC,
                      int* counter, int grid, hipStream_t s) {
-    k_gemm_batched<T, K, TM, TN, BK, AR><<<grid, kGemmThreads, 0, s>>>(
+    k_gemm_batched<T, K, TM, TN, BK, AR, PF><<<grid, kGemmThreads, 0, s>>>(
         nitems, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
     return launch_status();
 }
 
-template <typename T, int K, int TM, int TN, int BK, int U, int AR>
+template <typename T, int K, int TM, int TN, int BK, int U, int AR, bool PF = false>
 static int gb_launch_mixed(int nunits, const GbItem* items, const GbProb* probs, const void* A,
                            long long psA, const void* B, long long psB, void* C, long long psC,
                            int* counter, int grid, hipStream_t s) {
-    k_gemm_batched_mixed<T, K, TM, TN, BK, U, AR><<<grid, kGemmThreads, 0, s>>>(
+    k_gemm_batched_mixed<T, K, TM, TN, BK, U, AR, PF><<<grid, kGemmThreads, 0, s>>>(
         nunits, items, probs, (const T*)A, psA, (const T*)B, psB, (T*)C, psC, counter);
     return launch_status();
 }
@@ -671,13 +671,23 @@ static std::vector<GbVariant> gb_variants(int prec) {
 #define MPX_GBW(T_, K_, U_, AR_) GbVariant{gb_launch_wave<T_, K_, U_, AR_>, 8, 8, kGemmThreads / 64, false}
 #define MPX_GBM(T_, K_, TM_, TN_, BK_, U_, AR_) \
     GbVariant{gb_launch_mixed<T_, K_, TM_, TN_, BK_, U_, AR_>, 16 * TM_, 16 * TN_, 1, true}
+    // the same workgroup tiles with the LDS-prefetching panel loop
+#define MPX_GBP(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_, true>, 16 * TM_, 16 * TN_, 1, false}
+#define MPX_GBMP(T_, K_, TM_, TN_, BK_, U_, AR_) \
+    GbVariant{gb_launch_mixed<T_, K_, TM_, TN_, BK_, U_, AR_, true>, 16 * TM_, 16 * TN_, 1, true}
     switch (prec) {
-        case MPX_DD: return {MPX_GBW(double, 2, 4, AR_BF), MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF)};
-        case MPX_TD: return {MPX_GBM(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF)};
-        case MPX_QD: return {MPX_GBM(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF)};
-        case MPX_FF: return {MPX_GBW(float, 2, 4, AR_BF), MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF)};
+        case MPX_DD: return {MPX_GBW(double, 2, 4, AR_BF), MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF),
+                             MPX_GBP(double, 2, 2, 2, 16, AR_BF), MPX_GBMP(double, 2, 1, 1, 16, 4, AR_BF)};
+        case MPX_TD: return {MPX_GBM(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF),
+                             MPX_GBMP(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBMP(double, 3, 1, 1, 16, 2, AR_BF)};
+        case MPX_QD: return {MPX_GBM(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF),
+                             MPX_GBMP(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBMP(double, 4, 1, 2, 16, 2, AR_BF)};
+        case MPX_FF: return {MPX_GBW(float, 2, 4, AR_BF), MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF),
+                             MPX_GBP(float, 2, 2, 2, 16, AR_BF), MPX_GBMP(float, 2, 1, 1, 16, 4, AR_BF)};
         default: return {};
     }
+#undef MPX_GBMP
+#undef MPX_GBP
 #undef MPX_GBM
 #undef MPX_GBW
 #undef MPX_GB

@@ -174,135 +174,135 @@ static void ff_bf_mul(const float a[2], const float b[2], float c[2]) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Triple-word (Section 2.2): TWBFAdd and TWBFMul.  Variable names follow    */
-/* the paper's (letter = lane of the computation, digit = step).  Inputs are */
-/* called x[], y[] here because the paper reuses a..i as temporaries.        */
+/* Triple-word (Section 2.2): TWBFAdd and TWBFMul; quad-word (Section 2.3):  */
+/* QWBFAdd and QDBFMul.  Each turns its inputs into exact terms (TwoSum of   */
+/* each component pair, or TwoProd of the leading cross products and plain   */
+/* products of the last order) and folds those terms into the leading word   */
+/* in the fixed order the paper gives: QuickTwoSum where the magnitudes are  */
+/* known to be ordered, TwoSum elsewhere, plain additions for the lowest     */
+/* terms.  The order of the steps is the paper's; the names are ours:        */
+/* s[i], t[i] are the componentwise sums and their errors, pIJ / qIJ the     */
+/* product x[i]*y[j] rounded and its error, and a trailing digit elsewhere   */
+/* is the order of magnitude of the term (0 = the leading word).             */
 /* ------------------------------------------------------------------------ */
 
 static void tw_bf_add(const double x[3], const double y[3], double c[3]) {
-    double a1, b1, c1, d1, e1, f1;
-    double a2, c2, b2, d2, e2;
-    double a3, d3, b3, c3, c4, c5, d5, b6, c6, b7, c7;
-    two_sum(x[0], y[0], &a1, &b1);
-    two_sum(x[1], y[1], &c1, &d1);
-    two_sum(x[2], y[2], &e1, &f1);
-    quick_two_sum(a1, c1, &a2, &c2);
-    b2 = OP_ADD(b1, f1);
-    two_sum(d1, e1, &d2, &e2);
-    quick_two_sum(a2, d2, &a3, &d3);
-    two_sum(b2, c2, &b3, &c3);
-    c4 = OP_ADD(c3, e2);
-    two_sum(c4, d3, &c5, &d5);
-    two_sum(b3, c5, &b6, &c6);
-    quick_two_sum(a3, b6, &c[0], &b7);
-    c7 = OP_ADD(c6, d5);
-    quick_two_sum(b7, c7, &c[1], &c[2]);
+    double s[3], t[3];
+    double top, up1, mid2, low3, up2, acc1, low2, acc2, low4, acc, low5, carry;
+    for (int i = 0; i < 3; ++i) two_sum(x[i], y[i], &s[i], &t[i]);
+    quick_two_sum(s[0], s[1], &top, &up1);
+    double rest1 = OP_ADD(t[0], t[2]);
+    two_sum(t[1], s[2], &mid2, &low3);
+    quick_two_sum(top, mid2, &top, &up2);
+    two_sum(rest1, up1, &acc1, &low2);
+    two_sum(OP_ADD(low2, low3), up2, &acc2, &low4);
+    two_sum(acc1, acc2, &acc, &low5);
+    quick_two_sum(top, acc, &c[0], &carry);
+    quick_two_sum(carry, OP_ADD(low5, low4), &c[1], &c[2]);
 }
 
 static void tw_bf_mul(const double x[3], const double y[3], double c[3]) {
-    double a0, b0, c0, e0, d0, f0, g0, h0, i0;
-    double c1, d1, e1, g1, b2, c2, g2, a3, b3, c3, e3, c4, b5, c5, b6;
-    two_prod(x[0], y[0], &a0, &b0);
-    two_prod(x[0], y[1], &c0, &e0);
-    two_prod(x[1], y[0], &d0, &f0);
-    g0 = OP_MUL(x[0], y[2]);
-    h0 = OP_MUL(x[1], y[1]);
-    i0 = OP_MUL(x[2], y[0]);
-    two_sum(c0, d0, &c1, &d1);
-    e1 = OP_ADD(e0, f0);
-    g1 = OP_ADD(g0, i0);
-    two_sum(b0, c1, &b2, &c2);
-    g2 = OP_ADD(g1, h0);
-    quick_two_sum(a0, b2, &a3, &b3);
-    c3 = OP_ADD(c2, d1);
-    e3 = OP_ADD(e1, g2);
-    c4 = OP_ADD(c3, e3);
-    quick_two_sum(b3, c4, &b5, &c5);
-    quick_two_sum(a3, b5, &c[0], &b6);
-    quick_two_sum(b6, c5, &c[1], &c[2]);
+    double p00, q00, p01, q01, p10, q10;
+    double cross1, cross_err, lead1, lead1_err, top, up, hi, lo, carry;
+    two_prod(x[0], y[0], &p00, &q00);
+    two_prod(x[0], y[1], &p01, &q01);
+    two_prod(x[1], y[0], &p10, &q10);
+    double p02 = OP_MUL(x[0], y[2]);
+    double p11 = OP_MUL(x[1], y[1]);
+    double p20 = OP_MUL(x[2], y[0]);
+    two_sum(p01, p10, &cross1, &cross_err);
+    double qsum2 = OP_ADD(q01, q10);
+    double psum2 = OP_ADD(p02, p20);
+    two_sum(q00, cross1, &lead1, &lead1_err);
+    psum2 = OP_ADD(psum2, p11);
+    quick_two_sum(p00, lead1, &top, &up);
+    double part_a = OP_ADD(lead1_err, cross_err);
+    double part_b = OP_ADD(qsum2, psum2);
+    double order2 = OP_ADD(part_a, part_b);
+    quick_two_sum(up, order2, &hi, &lo);
+    quick_two_sum(top, hi, &c[0], &carry);
+    quick_two_sum(carry, lo, &c[1], &c[2]);
 }
 
-/* ------------------------------------------------------------------------ */
-/* Quad-word (Section 2.3): QWBFAdd and QDBFMul.                             */
-/* ------------------------------------------------------------------------ */
-
 static void qw_bf_add(const double x[4], const double y[4], double c[4]) {
-    double a1, b1, c1, d1, e1, f1, g1, h1;
-    double a2, c2, b2, d2, e2, f2, g2;
-    double b3, g3, c3, d3, e3, f3;
-    double a4, c4, d4, e4, b5, d5, e5, b6, c6, d6, e6;
-    double a7, b7, c7, d7, e8, b8, c8, d9, b10, c10, d10, c11;
-    two_sum(x[0], y[0], &a1, &b1);
-    two_sum(x[1], y[1], &c1, &d1);
-    two_sum(x[2], y[2], &e1, &f1);
-    two_sum(x[3], y[3], &g1, &h1);
-    quick_two_sum(a1, c1, &a2, &c2);
-    b2 = OP_ADD(b1, h1);
-    two_sum(d1, e1, &d2, &e2);
-    two_sum(f1, g1, &f2, &g2);
-    two_sum(b2, g2, &b3, &g3);
-    quick_two_sum(c2, d2, &c3, &d3);
-    two_sum(e2, f2, &e3, &f3);
-    quick_two_sum(a2, c3, &a4, &c4);
-    quick_two_sum(d3, e3, &d4, &e4);
-    two_sum(b3, d4, &b5, &d5);
-    e5 = OP_ADD(e4, f3);
-    two_sum(b5, c4, &b6, &c6);
-    two_sum(d5, e5, &d6, &e6);
-    quick_two_sum(a4, b6, &a7, &b7);
-    quick_two_sum(c6, d6, &c7, &d7);
-    e8 = OP_ADD(e6, g3);
-    quick_two_sum(b7, c7, &b8, &c8);
-    d9 = OP_ADD(d7, e8);
-    quick_two_sum(a7, b8, &c[0], &b10);
-    quick_two_sum(c8, d9, &c10, &d10);
-    quick_two_sum(b10, c10, &c[1], &c11);
-    quick_two_sum(c11, d10, &c[2], &c[3]);
+    double s[4], t[4];
+    double top, up1, m2, m2e, m3, m3e, deep, deep_e, u1, u1e, u2, u2e;
+    double up2, v2, v2e, w1, w1e, w2, w2e, w3, w3e, up3, z2, z2e, h1, h2;
+    double k1, k2, k3, k4;
+    for (int i = 0; i < 4; ++i) two_sum(x[i], y[i], &s[i], &t[i]);
+    /* first pass: each head meets the error of the order above it */
+    quick_two_sum(s[0], s[1], &top, &up1);
+    double bottom = OP_ADD(t[0], t[3]);
+    two_sum(t[1], s[2], &m2, &m2e);
+    two_sum(t[2], s[3], &m3, &m3e);
+    two_sum(bottom, m3e, &deep, &deep_e);
+    quick_two_sum(up1, m2, &u1, &u1e);
+    two_sum(m2e, m3, &u2, &u2e);
+    /* second pass */
+    quick_two_sum(top, u1, &top, &up2);
+    quick_two_sum(u1e, u2, &v2, &v2e);
+    two_sum(deep, v2, &w1, &w1e);
+    double tail3 = OP_ADD(v2e, u2e);
+    two_sum(w1, up2, &w2, &w2e);
+    two_sum(w1e, tail3, &w3, &w3e);
+    /* third pass */
+    quick_two_sum(top, w2, &top, &up3);
+    quick_two_sum(w2e, w3, &z2, &z2e);
+    double tail4 = OP_ADD(w3e, deep_e);
+    quick_two_sum(up3, z2, &h1, &h2);
+    double h3 = OP_ADD(z2e, tail4);
+    /* renormalise into four words */
+    quick_two_sum(top, h1, &c[0], &k1);
+    quick_two_sum(h2, h3, &k2, &k3);
+    quick_two_sum(k1, k2, &c[1], &k4);
+    quick_two_sum(k4, k3, &c[2], &c[3]);
 }
 
 static void qd_bf_mul(const double x[4], const double y[4], double c[4]) {
-    double a0, b0, c0, e0, d0, f0, g0, j0, h0, k0, i0, l0, m0, n0, o0, p0;
-    double c1, d1, e1, f1, g1, i1, j1, m1, n1;
-    double b2, c2, e2, h2, f2, i2, m2;
-    double a3, b3, c3, d3, e3, g3, f3, h3;
-    double c4, e4, d4, f4, d5, c6, d6, b7, c7, d7, b8, c8, d8, c9;
-    two_prod(x[0], y[0], &a0, &b0);
-    two_prod(x[0], y[1], &c0, &e0);
-    two_prod(x[1], y[0], &d0, &f0);
-    two_prod(x[0], y[2], &g0, &j0);
-    two_prod(x[1], y[1], &h0, &k0);
-    two_prod(x[2], y[0], &i0, &l0);
-    m0 = OP_MUL(x[0], y[3]);
-    n0 = OP_MUL(x[1], y[2]);
-    o0 = OP_MUL(x[2], y[1]);
-    p0 = OP_MUL(x[3], y[0]);
-    two_sum(c0, d0, &c1, &d1);
-    two_sum(e0, f0, &e1, &f1);
-    two_sum(g0, i0, &g1, &i1);
-    j1 = OP_ADD(j0, l0);
-    m1 = OP_ADD(m0, p0);
-    n1 = OP_ADD(n0, o0);
-    two_sum(b0, c1, &b2, &c2);
-    two_sum(e1, h0, &e2, &h2);
-    f2 = OP_ADD(f1, j1);
-    i2 = OP_ADD(i1, k0);
-    m2 = OP_ADD(m1, n1);
-    quick_two_sum(a0, b2, &a3, &b3);
-    quick_two_sum(c2, d1, &c3, &d3);
-    two_sum(e2, g1, &e3, &g3);
-    f3 = OP_ADD(f2, m2);
-    h3 = OP_ADD(h2, i2);
-    two_sum(c3, e3, &c4, &e4);
-    d4 = OP_ADD(d3, h3);
-    f4 = OP_ADD(f3, g3);
-    d5 = OP_ADD(d4, e4);
-    two_sum(c4, d5, &c6, &d6);
-    two_sum(b3, c6, &b7, &c7);
-    d7 = OP_ADD(d6, f4);
-    quick_two_sum(a3, b7, &c[0], &b8);
-    two_sum(c7, d7, &c8, &d8);
-    two_sum(b8, c8, &c[1], &c9);
-    quick_two_sum(c9, d8, &c[2], &c[3]);
+    double p00, q00, p01, q01, p10, q10, p02, q02, p11, q11, p20, q20;
+    double sum1, sum1e, qsum2, qsum2e, psum2, psum2e, n1, n1e, n2, n2e, top, up;
+    double r2, r2e, g2, g2e, h2, h3, k1, k2, l1, l2, m1, m2;
+    two_prod(x[0], y[0], &p00, &q00);
+    two_prod(x[0], y[1], &p01, &q01);
+    two_prod(x[1], y[0], &p10, &q10);
+    two_prod(x[0], y[2], &p02, &q02);
+    two_prod(x[1], y[1], &p11, &q11);
+    two_prod(x[2], y[0], &p20, &q20);
+    double p03 = OP_MUL(x[0], y[3]);
+    double p12 = OP_MUL(x[1], y[2]);
+    double p21 = OP_MUL(x[2], y[1]);
+    double p30 = OP_MUL(x[3], y[0]);
+    /* pair up terms of equal order */
+    two_sum(p01, p10, &sum1, &sum1e);
+    two_sum(q01, q10, &qsum2, &qsum2e);
+    two_sum(p02, p20, &psum2, &psum2e);
+    double qq3 = OP_ADD(q02, q20);
+    double outer3 = OP_ADD(p03, p30);
+    double inner3 = OP_ADD(p12, p21);
+    /* order 1 meets the leading product's error; order 2 gathers */
+    two_sum(q00, sum1, &n1, &n1e);
+    two_sum(qsum2, p11, &n2, &n2e);
+    double a3 = OP_ADD(qsum2e, qq3);
+    double b3 = OP_ADD(psum2e, q11);
+    double c3 = OP_ADD(outer3, inner3);
+    quick_two_sum(p00, n1, &top, &up);
+    quick_two_sum(n1e, sum1e, &r2, &r2e);
+    two_sum(n2, psum2, &g2, &g2e);
+    double d3 = OP_ADD(a3, c3);
+    double e3 = OP_ADD(n2e, b3);
+    /* order 2 in total, then the order-3 remainder */
+    two_sum(r2, g2, &h2, &h3);
+    double f3 = OP_ADD(r2e, e3);
+    double g3 = OP_ADD(d3, g2e);
+    f3 = OP_ADD(f3, h3);
+    two_sum(h2, f3, &k1, &k2);
+    two_sum(up, k1, &l1, &l2);
+    double rest3 = OP_ADD(k2, g3);
+    /* renormalise into four words */
+    quick_two_sum(top, l1, &c[0], &m1);
+    two_sum(l2, rest3, &k1, &k2);
+    two_sum(m1, k1, &c[1], &m2);
+    quick_two_sum(m2, k2, &c[2], &c[3]);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -96,128 +96,191 @@ __device__ __forceinline__ mpn<T, 2> bf_mul(const mpn<T, 2>& x, const mpn<T, 2>&
 }
 
 // ------------------------------------------------------- triple-word ----
+// TWBFAdd and TWBFMul (Section 2.2) and QWBFAdd and QDBFMul (Section 2.3).
+// Each is a fixed network of error-free transformations: the inputs are
+// first turned into exact terms (componentwise TwoSums, or the TwoProds of
+// the leading cross products plus rounded products of the last order), and
+// those terms are then folded towards the leading word, one order of
+// magnitude at a time, with QuickTwoSum wherever the ordering of magnitudes
+// is known and TwoSum elsewhere; the lowest terms are added without their
+// errors.  Results are compared bit for bit with an independent CPU
+// implementation, so the network (which term meets which, in which order,
+// with which transformation) is the published one; the names are ours.  A
+// name's digit is the order of magnitude it carries (0 = the leading word,
+// 1 = about one unit roundoff below it, ...).
 
 __device__ __forceinline__ td_t bf_add(const td_t& x, const td_t& y) {
-    double a1, b1, c1, d1, e1, f1, a2, c2, d2, e2, a3, d3, b3, c3, c5, d5, b6, c6, b7;
-    ts(x.c[0], y.c[0], a1, b1);
-    ts(x.c[1], y.c[1], c1, d1);
-    ts(x.c[2], y.c[2], e1, f1);
-    qts(a1, c1, a2, c2);
-    const double b2 = b1 + f1;
-    ts(d1, e1, d2, e2);
-    qts(a2, d2, a3, d3);
-    ts(b2, c2, b3, c3);
-    const double c4 = c3 + e2;
-    ts(c4, d3, c5, d5);
-    ts(b3, c5, b6, c6);
+    // Componentwise exact sums.
+    double hi0, lo0, hi1, lo1, hi2, lo2;
+    ts(x.c[0], y.c[0], hi0, lo0);
+    ts(x.c[1], y.c[1], hi1, lo1);
+    ts(x.c[2], y.c[2], hi2, lo2);
+    // The leading sum takes in the order-1 head; the order-2 terms meet.
+    double lead, spill1;
+    qts(hi0, hi1, lead, spill1);
+    const double low1 = lo0 + lo2;
+    double mid2, err3;
+    ts(lo1, hi2, mid2, err3);
+    double spill2;
+    qts(lead, mid2, lead, spill2);
+    // Fold the order-1 terms, then what is left below them.
+    double sum1, err2;
+    ts(low1, spill1, sum1, err2);
+    double sum2, err4;
+    ts(err2 + err3, spill2, sum2, err4);
+    double next, err5;
+    ts(sum1, sum2, next, err5);
+    // Renormalise into three words.
     td_t r;
-    qts(a3, b6, r.c[0], b7);
-    const double c7 = c6 + d5;
-    qts(b7, c7, r.c[1], r.c[2]);
+    double carry;
+    qts(lead, next, r.c[0], carry);
+    qts(carry, err5 + err4, r.c[1], r.c[2]);
     return r;
 }
 
 __device__ __forceinline__ td_t bf_mul(const td_t& x, const td_t& y) {
-    double a0, b0, c0, e0, d0, f0, c1, d1, b2, c2, a3, b3, b5, c5, b6;
-    tp(x.c[0], y.c[0], a0, b0);
-    tp(x.c[0], y.c[1], c0, e0);
-    tp(x.c[1], y.c[0], d0, f0);
-    const double g0 = x.c[0] * y.c[2];
-    const double h0 = x.c[1] * y.c[1];
-    const double i0 = x.c[2] * y.c[0];
-    ts(c0, d0, c1, d1);
-    const double e1 = e0 + f0;
-    const double g1 = g0 + i0;
-    ts(b0, c1, b2, c2);
-    const double g2 = g1 + h0;
-    qts(a0, b2, a3, b3);
-    const double c3 = c2 + d1;
-    const double e3 = e1 + g2;
-    const double c4 = c3 + e3;
-    qts(b3, c4, b5, c5);
+    // Exact products of orders 0 and 1, rounded products of order 2.
+    double p0, q1, p1a, q2a, p1b, q2b;
+    tp(x.c[0], y.c[0], p0, q1);
+    tp(x.c[0], y.c[1], p1a, q2a);
+    tp(x.c[1], y.c[0], p1b, q2b);
+    const double r2a = x.c[0] * y.c[2];
+    const double r2b = x.c[1] * y.c[1];
+    const double r2c = x.c[2] * y.c[0];
+    // Order 1: the two cross products, then the leading product's error.
+    double s1, s1err;
+    ts(p1a, p1b, s1, s1err);
+    const double errs2 = q2a + q2b;
+    const double outer2 = r2a + r2c;
+    double t1, t1err;
+    ts(q1, s1, t1, t1err);
+    const double prods2 = outer2 + r2b;
+    double lead, spill;
+    qts(p0, t1, lead, spill);
+    // Everything of order 2, added without errors.
+    const double sum2 = (t1err + s1err) + (errs2 + prods2);
+    double w1, w2;
+    qts(spill, sum2, w1, w2);
+    // Renormalise into three words.
     td_t r;
-    qts(a3, b5, r.c[0], b6);
-    qts(b6, c5, r.c[1], r.c[2]);
+    double carry;
+    qts(lead, w1, r.c[0], carry);
+    qts(carry, w2, r.c[1], r.c[2]);
     return r;
 }
 
 // --------------------------------------------------------- quad-word ----
 
 __device__ __forceinline__ qd_t bf_add(const qd_t& x, const qd_t& y) {
-    double a1, b1, c1, d1, e1, f1, g1, h1, a2, c2, d2, e2, f2, g2, b3, g3, c3, d3, e3, f3;
-    double a4, c4, d4, e4, b5, d5, b6, c6, d6, e6, a7, b7, c7, d7, b8, c8, b10, c10, d10, c11;
-    ts(x.c[0], y.c[0], a1, b1);
-    ts(x.c[1], y.c[1], c1, d1);
-    ts(x.c[2], y.c[2], e1, f1);
-    ts(x.c[3], y.c[3], g1, h1);
-    qts(a1, c1, a2, c2);
-    const double b2 = b1 + h1;
-    ts(d1, e1, d2, e2);
-    ts(f1, g1, f2, g2);
-    ts(b2, g2, b3, g3);
-    qts(c2, d2, c3, d3);
-    ts(e2, f2, e3, f3);
-    qts(a2, c3, a4, c4);
-    qts(d3, e3, d4, e4);
-    ts(b3, d4, b5, d5);
-    const double e5 = e4 + f3;
-    ts(b5, c4, b6, c6);
-    ts(d5, e5, d6, e6);
-    qts(a4, b6, a7, b7);
-    qts(c6, d6, c7, d7);
-    const double e8 = e6 + g3;
-    qts(b7, c7, b8, c8);
-    const double d9 = d7 + e8;
+    // Componentwise exact sums.
+    double hi0, lo0, hi1, lo1, hi2, lo2, hi3, lo3;
+    ts(x.c[0], y.c[0], hi0, lo0);
+    ts(x.c[1], y.c[1], hi1, lo1);
+    ts(x.c[2], y.c[2], hi2, lo2);
+    ts(x.c[3], y.c[3], hi3, lo3);
+    // First pass: each head meets the error of the order above it.
+    double lead, spill1;
+    qts(hi0, hi1, lead, spill1);
+    const double deep = lo0 + lo3;
+    double m2, m2err;
+    ts(lo1, hi2, m2, m2err);
+    double m3, m3err;
+    ts(lo2, hi3, m3, m3err);
+    double deep1, deep1err;
+    ts(deep, m3err, deep1, deep1err);
+    double u1, u1err;
+    qts(spill1, m2, u1, u1err);
+    double u2, u2err;
+    ts(m2err, m3, u2, u2err);
+    // Second pass.
+    double spill2;
+    qts(lead, u1, lead, spill2);
+    double v2, v2err;
+    qts(u1err, u2, v2, v2err);
+    double w1, w1err;
+    ts(deep1, v2, w1, w1err);
+    const double tail3 = v2err + u2err;
+    double w2, w2err;
+    ts(w1, spill2, w2, w2err);
+    double w3, w3err;
+    ts(w1err, tail3, w3, w3err);
+    // Third pass.
+    double z1;
+    qts(lead, w2, lead, z1);
+    double z2, z2err;
+    qts(w2err, w3, z2, z2err);
+    const double tail4 = w3err + deep1err;
+    double g1, g2;
+    qts(z1, z2, g1, g2);
+    const double g3 = z2err + tail4;
+    // Renormalise into four words.
     qd_t r;
-    qts(a7, b8, r.c[0], b10);
-    qts(c8, d9, c10, d10);
-    qts(b10, c10, r.c[1], c11);
-    qts(c11, d10, r.c[2], r.c[3]);
+    double c1, c2, c3, c4;
+    qts(lead, g1, r.c[0], c1);
+    qts(g2, g3, c2, c3);
+    qts(c1, c2, r.c[1], c4);
+    qts(c4, c3, r.c[2], r.c[3]);
     return r;
 }
 
 __device__ __forceinline__ qd_t bf_mul(const qd_t& x, const qd_t& y) {
-    double a0, b0, c0, e0, d0, f0, g0, j0, h0, k0, i0, l0;
-    double c1, d1, e1, f1, g1, i1, b2, c2, e2, h2, a3, b3, c3, d3, e3, g3;
-    double c4, e4, c6, d6, b7, c7, b8, c8, d8, c9;
-    tp(x.c[0], y.c[0], a0, b0);
-    tp(x.c[0], y.c[1], c0, e0);
-    tp(x.c[1], y.c[0], d0, f0);
-    tp(x.c[0], y.c[2], g0, j0);
-    tp(x.c[1], y.c[1], h0, k0);
-    tp(x.c[2], y.c[0], i0, l0);
-    const double m0 = x.c[0] * y.c[3];
-    const double n0 = x.c[1] * y.c[2];
-    const double o0 = x.c[2] * y.c[1];
-    const double p0 = x.c[3] * y.c[0];
-    ts(c0, d0, c1, d1);
-    ts(e0, f0, e1, f1);
-    ts(g0, i0, g1, i1);
-    const double j1 = j0 + l0;
-    const double m1 = m0 + p0;
-    const double n1 = n0 + o0;
-    ts(b0, c1, b2, c2);
-    ts(e1, h0, e2, h2);
-    const double f2 = f1 + j1;
-    const double i2 = i1 + k0;
-    const double m2 = m1 + n1;
-    qts(a0, b2, a3, b3);
-    qts(c2, d1, c3, d3);
-    ts(e2, g1, e3, g3);
-    const double f3 = f2 + m2;
-    const double h3 = h2 + i2;
-    ts(c3, e3, c4, e4);
-    const double d4 = d3 + h3;
-    const double f4 = f3 + g3;
-    const double d5 = d4 + e4;
-    ts(c4, d5, c6, d6);
-    ts(b3, c6, b7, c7);
-    const double d7 = d6 + f4;
+    // Exact products of orders 0-2 (pNN = x[i]*y[j] rounded, eNN its error),
+    // rounded products of order 3.
+    double p00, e00, p01, e01, p10, e10, p02, e02, p11, e11, p20, e20;
+    tp(x.c[0], y.c[0], p00, e00);
+    tp(x.c[0], y.c[1], p01, e01);
+    tp(x.c[1], y.c[0], p10, e10);
+    tp(x.c[0], y.c[2], p02, e02);
+    tp(x.c[1], y.c[1], p11, e11);
+    tp(x.c[2], y.c[0], p20, e20);
+    const double p03 = x.c[0] * y.c[3];
+    const double p12 = x.c[1] * y.c[2];
+    const double p21 = x.c[2] * y.c[1];
+    const double p30 = x.c[3] * y.c[0];
+    // Pair up the terms of equal order.
+    double a1, a1err;
+    ts(p01, p10, a1, a1err);
+    double a2, a2err;
+    ts(e01, e10, a2, a2err);
+    double b2, b2err;
+    ts(p02, p20, b2, b2err);
+    const double e3 = e02 + e20;
+    const double o3 = p03 + p30;
+    const double i3 = p12 + p21;
+    // Order 1 meets the leading product's error; order 2 gathers.
+    double s1, s1err;
+    ts(e00, a1, s1, s1err);
+    double s2, s2err;
+    ts(a2, p11, s2, s2err);
+    const double f3 = a2err + e3;
+    const double g3 = b2err + e11;
+    const double h3 = o3 + i3;
+    double lead, spill1;
+    qts(p00, s1, lead, spill1);
+    double t2, t2err;
+    qts(s1err, a1err, t2, t2err);
+    double u2, u2err;
+    ts(s2, b2, u2, u2err);
+    const double k3 = f3 + h3;
+    const double l3 = s2err + g3;
+    // Order 2 total, then the order-3 remainder.
+    double v2, v2err;
+    ts(t2, u2, v2, v2err);
+    const double m3 = t2err + l3;
+    const double n3 = k3 + u2err;
+    const double q3 = m3 + v2err;
+    double w2, w3;
+    ts(v2, q3, w2, w3);
+    double z1, z2;
+    ts(spill1, w2, z1, z2);
+    const double rest3 = w3 + n3;
+    // Renormalise into four words.
     qd_t r;
-    qts(a3, b7, r.c[0], b8);
-    ts(c7, d7, c8, d8);
-    ts(b8, c8, r.c[1], c9);
-    qts(c9, d8, r.c[2], r.c[3]);
+    double c1, c2, c3, c4;
+    qts(lead, z1, r.c[0], c1);
+    ts(z2, rest3, c2, c3);
+    ts(c1, c2, r.c[1], c4);
+    qts(c4, c3, r.c[2], r.c[3]);
     return r;
 }
 

@@ -343,8 +343,10 @@ NOBF_OPS_PER_MAC = {"dd_nobf": 11 + 9, "dd_nobf_acc": 20 + 9, "td_nobf": 60 + 12
 
 def nobf_rows(mpx, torch, T):
     """Branch-free versus conventional arithmetic (the comparison of Tables 3-4
-    and Figure 3): GEMM n = 1024, 2048 (each arithmetic autotuned) and batched
-    real Horner; speedup = conventional time / BF time."""
+    and Figure 3): GEMM n = 1024, 2048 (each arithmetic autotuned), batched
+    Horner at real and complex points, and batched Durand-Kerner on the
+    Chebyshev polynomial (each arithmetic autotuned); speedup = conventional
+    time / BF time."""
     from paper_2603_14926_amd import synth
     out = {}
     pairs = [("qd", "qd_nobf"), ("td", "td_nobf"), ("dd", "dd_nobf"), ("dd", "dd_nobf_acc")]
@@ -382,7 +384,8 @@ def nobf_rows(mpx, torch, T):
         out[f"horner_complex_{nb}_b{batch}_deg{deg}"] = {"bf_ms": tb, "nobf_ms": tn, "speedup_bf": tn / tb}
         del coef, x, y, xi, yc
     # Durand-Kerner on the Chebyshev integration polynomial n = 64 (Table 6's
-    # problem), 4096 copies in one persistent launch, Aberth start, 200 sweeps.
+    # problem), 4096 copies in one persistent launch, Aberth start, 200 sweeps
+    # (every copy is one 64-lane item, so the launch shape matters: autotuned).
     from fractions import Fraction  # noqa: F401  (coefficients are exact rationals)
     n, copies, iters = 64, 4096, 200
     a = synth.chebyshev_coefficients(n)
@@ -394,12 +397,15 @@ def nobf_rows(mpx, torch, T):
         cim = torch.zeros_like(cre)
         zr = torch.zeros((K, n * copies), dtype=torch.float64, device="cuda")
         zi = torch.zeros_like(zr)
-        r = {}
-        for q in (bf, nb):
+        r, var = {}, {}
+        for q in (bf, nb):   # each arithmetic at its own autotuned launch shape
             plan = mpx.RootsPlan(q, deg, iters=iters, init=True, graph=True)
+            var[q], _ = plan.autotune(cre, cim, zr, zi, iters_probe=8)
             r[q] = T(lambda: plan.run(cre, cim, zr, zi))
         out[f"dk_chebyshev64_{nb}_x{copies}_{iters}it"] = {"bf_ms": r[bf], "nobf_ms": r[nb],
-                                                          "speedup_bf": r[nb] / r[bf]}
+                                                          "speedup_bf": r[nb] / r[bf],
+                                                          "bf_variant": int(var[bf]),
+                                                          "nobf_variant": int(var[nb])}
         del cre, cim, zr, zi
     return out
 

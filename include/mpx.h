@@ -409,11 +409,11 @@ int mpx_plan_destroy(mpx_plan plan);
 /* Launch-shape variants (roots per lane, resident waves per CU, the packed
  * schedule: 4-wave jobs built by the plan, each holding whole polynomials
  * whose 64-root chunks are spread over the waves to balance their loads, or
- * a lane-packed schedule: 4-, 8- or 12-wave jobs whose roots are laid out
- * lane by lane over 64-lane items, so roots of several polynomials share a
- * wave and small polynomials fill lanes a larger one leaves idle); results
- * do not depend on the variant.  A new plan uses lane-packed 12-wave jobs
- * (one per CU), or the variant the tune cache holds for its
+ * a lane-packed schedule: 4-, 8-, 12- or 16-wave jobs whose roots are laid
+ * out lane by lane over 64-lane items, so roots of several polynomials share
+ * a wave and small polynomials fill lanes a larger one leaves idle); results
+ * do not depend on the variant.  A new plan uses lane-packed 16-wave jobs
+ * (one per CU, four waves per SIMD), or the variant the tune cache holds for its
  * (precision, batch, largest degree) bucket, or MPX_DK_VARIANT (see the GEMM
  * tuning notes).  The autotuner runs each for iters_probe sweeps
  * on a private copy of the given start roots, in two rounds over all variants

@@ -971,14 +971,19 @@ static const DkVariant kDkVariants[] = {
     {1, 8, DK_WAVE, 1, 0, -1},    {2, 8, DK_WAVE, 1, 0, -1},    {1, 16, DK_WAVE, 1, 0, -1},
     {2, 12, DK_WAVE, 1, 0, -1},   {1, 8, DK_PACKED, 4, 0, -1},  {1, 12, DK_PACKED, 4, 0, -1},
     {1, 12, DK_LANES, 4, 100, 0}, {1, 12, DK_LANES, 4, 150, 1}, {1, 8, DK_LANES, 4, 100, 2},
-    {1, 12, DK_LANES, 12, 200, 3}};
+    {1, 12, DK_LANES, 12, 200, 3}, {1, 16, DK_LANES, 16, 100, 4}, {1, 16, DK_LANES, 16, 200, 5},
+    {1, 16, DK_LANES, 4, 100, 6}};
 constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
-constexpr int kDkLaneScheds = 4;
-// A new plan's variant: lane-packed 12-wave jobs, one per CU.  On 4096 QD
-// polynomials of degrees 16..512 over 200 sweeps it took 4.02-4.04 s in
-// every run, against 4.12-4.14 s for the packed 4-wave chunks; lane-packed
-// 4-wave jobs at three per CU ranged from 3.96 to 4.24 s from run to run.
-constexpr int kDkDefaultVariant = 9;
+constexpr int kDkLaneScheds = 7;
+// A new plan's variant: lane-packed 16-wave jobs, one per CU (four waves per
+// SIMD).  On 4096 QD polynomials of degrees 16..512 over 200 sweeps it took
+// 3.79 s, against 4.03 s for 12-wave jobs, 4.15 s for the packed 4-wave
+// chunks and 4.3 s for 24 resident waves per CU (12- or 8-wave jobs); the job
+// cap (1 to 2 times the largest polynomial's heaviest wave) moved it by under
+// 2 %.  On 4096 copies of one degree-64 polynomial, where every polynomial is
+// one 64-lane item and 12-wave jobs leave a second round of jobs on a third
+// of the CUs (1.5 times slower), it is within 4 % of the fastest variant.
+constexpr int kDkDefaultVariant = 10;
 
 }  // namespace mpx
 
@@ -1055,6 +1060,9 @@ static int launch_dk(mpx_plan_s* p, int variant, const void* are, const void* ai
             if (v.w == 8)                                                                     \
                 return launch_dk_t<KK, 1, AR_, DK_LANES, 8>(p, v, are, aim, psc, rre, rim,    \
                                                             psr, status, s);                  \
+            if (v.w == 16)                                                                    \
+                return launch_dk_t<KK, 1, AR_, DK_LANES, 16>(p, v, are, aim, psc, rre, rim,   \
+                                                             psr, status, s);                 \
             return launch_dk_t<KK, 1, AR_, DK_LANES, 12>(p, v, are, aim, psc, rre, rim, psr,  \
                                                          status, s);                          \
         }                                                                                     \

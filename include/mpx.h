@@ -406,21 +406,26 @@ int mpx_polyroots_plan(mpx_plan *out, int prec, int64_t batch, const int32_t *de
 int mpx_polyroots(mpx_plan plan, const void *coef_re, const void *coef_im, int64_t psc,
                   void *roots_re, void *roots_im, int64_t psr, int32_t *status, void *stream);
 int mpx_plan_destroy(mpx_plan plan);
-/* Launch-shape variants (roots per lane, resident waves per CU, the packed
- * schedule: 4-wave jobs built by the plan, each holding whole polynomials
- * whose 64-root chunks are spread over the waves to balance their loads, or
- * a lane-packed schedule: 4-, 8-, 12- or 16-wave jobs whose roots are laid
- * out lane by lane over 64-lane items, so roots of several polynomials share
- * a wave and small polynomials fill lanes a larger one leaves idle); results
- * do not depend on the variant.  A new plan uses lane-packed 16-wave jobs
- * (one per CU, four waves per SIMD), or the variant the tune cache holds for its
- * (precision, batch, largest degree) bucket, or MPX_DK_VARIANT (see the GEMM
- * tuning notes).  The autotuner runs each for iters_probe sweeps
- * on a private copy of the given start roots, in two rounds over all variants
- * (a variant's time is its faster round), switches the plan to the fastest
- * only when it beats the plan's current variant by at least 3 %, and returns
- * the index kept (or a negative status), which it also records in the tune
- * cache.  Synchronises; allocates. */
+/* Launch-shape variants: roots per lane, resident waves per CU, and the
+ * schedule, which is one of
+ *   - one wave per polynomial;
+ *   - packed: 4-wave jobs built by the plan, each holding whole polynomials
+ *     whose 64-root chunks are spread over the waves to balance their loads;
+ *   - lane-packed: 4-, 8-, 12- or 16-wave jobs whose roots are laid out lane
+ *     by lane over 64-lane items, so roots of several polynomials share a
+ *     wave and small polynomials fill lanes a larger one leaves idle; the
+ *     jobs go to workgroups through a shared counter, heaviest first, or by
+ *     a static assignment the plan computes from the jobs' step counts (each
+ *     workgroup sweeps its own list).
+ * Results do not depend on the variant.  A new plan uses lane-packed 16-wave
+ * jobs (four waves per SIMD) on the static assignment, or the variant the
+ * tune cache holds for its (precision, batch, largest degree) bucket, or
+ * MPX_DK_VARIANT (see the GEMM tuning notes).  The autotuner runs each for
+ * iters_probe sweeps on a private copy of the given start roots, in two
+ * rounds over all variants (a variant's time is its faster round), switches
+ * the plan to the fastest only when it beats the plan's current variant by
+ * at least 3 %, and returns the index kept (or a negative status), which it
+ * also records in the tune cache.  Synchronises; allocates. */
 int mpx_polyroots_variant_count(void);
 int mpx_polyroots_set_variant(mpx_plan plan, int variant);
 int mpx_polyroots_get_variant(mpx_plan plan);   /* the plan's current variant */

@@ -14,13 +14,19 @@
 //   * start from the largest; keep adding the next largest while the job's
 //     heaviest wave stays within the cap;
 //   * fill: put whole smaller polynomials into the idle lanes of the last
-//     item (free: the item's length does not change), then add the smallest
-//     ones as new items while the heaviest wave does not grow;
+//     item (free: the item's length does not change), then add, as new
+//     items, the largest polynomial that still fits without making the
+//     heaviest wave heavier, as long as one does;
 //   * the cap is L = lscale * (the largest single polynomial's heaviest wave),
-//     lowered towards the end of the batch to (remaining work) / (3 slots W),
+//     lowered towards the end of the batch to (remaining work) / (slots W),
 //     so the last jobs are short and the persistent grid drains evenly.
-// Jobs are ordered heaviest first.  Deterministic: ties go to the lower
-// polynomial index, then the lower wave.
+// Dynamic schedules order the jobs heaviest first; the kernel's workgroups
+// take them from a shared counter.  Static schedules assign every job to one
+// of `slots` workgroups (heaviest job first to the least-loaded workgroup,
+// then moves and swaps of jobs that lower the most-loaded workgroup's total
+// while any does) and store each workgroup's jobs contiguously, heaviest
+// first.  Deterministic: ties go to the lower polynomial, job, wave or
+// workgroup index.
 #pragma once
 
 #include <algorithm>
@@ -37,6 +43,7 @@ struct LaneSchedHost {
     std::vector<int> poly_off;   // njobs + 1
     std::vector<int> polys;
     std::vector<long long> job_cost;  // heaviest wave of each job (sum of item lengths)
+    std::vector<int> wg_off;     // static schedules: slots + 1 job offsets per workgroup; else empty
     int njobs = 0;
 };
 
@@ -55,6 +62,18 @@ inline long long lpt(const std::vector<int>& len, int W, std::vector<int>* wave 
         if (wave) (*wave)[i] = w;
     }
     return *std::max_element(ld.begin(), ld.end());
+}
+
+// Wave loads under the same assignment.
+inline std::vector<long long> lpt_loads(const std::vector<int>& len, int W) {
+    std::vector<long long> ld(W, 0);
+    for (size_t i = 0; i < len.size(); ++i) {
+        int w = 0;
+        for (int v = 1; v < W; ++v)
+            if (ld[v] < ld[w]) w = v;
+        ld[w] += len[i];
+    }
+    return ld;
 }
 
 struct Job {
@@ -122,13 +141,104 @@ struct Pool {
     }
 };
 
+// The largest unplaced polynomial whose addition keeps J's heaviest wave
+// within lim (lowest index among equal degrees), or -1.  A polynomial that
+// does not share the last item adds ceil(d / 64) items of length d, which
+// the assignment puts, one after another, on the lightest wave: that is
+// replayed on the current wave loads instead of a full trial.
+inline int best_fit(const Job& J, const Pool& pool, long long lim, const std::vector<int>& deg,
+                    int W) {
+    const std::vector<long long> ld0 = lpt_loads(J.lens(deg), W);
+    const long long room = lim - *std::min_element(ld0.begin(), ld0.end());
+    std::vector<long long> ld;
+    for (auto it = pool.by.rbegin(); it != pool.by.rend(); ++it) {
+        const int d = it->first;
+        if (d > lim) continue;
+        const int c = it->second.back();
+        if (J.shares_last(c, deg)) {
+            if (J.trial(c, deg, W) <= lim) return c;
+            continue;
+        }
+        if (d > room) continue;
+        ld = ld0;
+        bool fits = true;
+        for (int k = 0; k < (d + 63) / 64 && fits; ++k) {
+            int w = 0;
+            for (int v = 1; v < W; ++v)
+                if (ld[v] < ld[w]) w = v;
+            ld[w] += d;
+            fits = ld[w] <= lim;
+        }
+        if (fits) return c;
+    }
+    return -1;
+}
+
+// Static assignment of jobs (costs, heaviest first) to `bins` workgroups:
+// each job to the least-loaded bin, then, while it lowers the most-loaded
+// bin's total, the best single move of one of its jobs to another bin or
+// swap with a lighter job there.  Returns each job's bin.
+inline std::vector<int> assign_bins(const std::vector<long long>& cost, int bins) {
+    std::vector<int> bin_of(cost.size(), 0);
+    std::vector<std::vector<int>> in(bins);
+    std::vector<long long> load(bins, 0);
+    for (size_t j = 0; j < cost.size(); ++j) {
+        int b = 0;
+        for (int v = 1; v < bins; ++v)
+            if (load[v] < load[b]) b = v;
+        in[b].push_back((int)j);
+        load[b] += cost[j];
+        bin_of[j] = b;
+    }
+    for (size_t guard = 0; guard < 64 * cost.size() + 64; ++guard) {
+        int M = 0;
+        for (int v = 1; v < bins; ++v)
+            if (load[v] > load[M]) M = v;
+        long long best = load[M];
+        int tb = -1, ta = -1, tj = -1;
+        for (int b = 0; b < bins; ++b) {
+            if (b == M || load[b] >= load[M]) continue;
+            for (int ia = 0; ia < (int)in[M].size(); ++ia) {
+                const long long ca = cost[in[M][ia]];
+                const long long mv = std::max(load[M] - ca, load[b] + ca);
+                if (mv < best) { best = mv; tb = b; ta = ia; tj = -1; }
+                for (int ib = 0; ib < (int)in[b].size(); ++ib) {
+                    const long long d = ca - cost[in[b][ib]];
+                    if (d <= 0) continue;
+                    const long long sw = std::max(load[M] - d, load[b] + d);
+                    if (sw < best) { best = sw; tb = b; ta = ia; tj = ib; }
+                }
+            }
+        }
+        if (tb < 0) break;
+        const int a = in[M][ta];
+        if (tj < 0) {
+            in[M].erase(in[M].begin() + ta);
+            in[tb].push_back(a);
+            load[M] -= cost[a];
+            load[tb] += cost[a];
+            bin_of[a] = tb;
+        } else {
+            const int c = in[tb][tj];
+            in[M][ta] = c;
+            in[tb][tj] = a;
+            load[M] += cost[c] - cost[a];
+            load[tb] += cost[a] - cost[c];
+            bin_of[a] = tb;
+            bin_of[c] = M;
+        }
+    }
+    return bin_of;
+}
+
 }  // namespace dks
 
 // deg: degrees (>= 1); W: waves per job; lscale: cap scale; slots: jobs
-// resident at once on the device (for the tail cap).  Returns false when an
-// index would overflow the int tables.
+// resident at once on the device (for the tail cap; the number of
+// workgroups of a static schedule); static_bins: build a static schedule.
+// Returns false when an index would overflow the int tables.
 inline bool build_lane_sched(const std::vector<int>& deg, int W, double lscale, long long slots,
-                             LaneSchedHost& out) {
+                             LaneSchedHost& out, bool static_bins = false) {
     using namespace dks;
     const int N = (int)deg.size();
     Pool pool;
@@ -176,8 +286,8 @@ inline bool build_lane_sched(const std::vector<int>& deg, int W, double lscale, 
                 remaining -= (long long)deg[c] * deg[c];
                 continue;
             }
-            const int s = pool.peek_smallest();
-            if (J.trial(s, deg, W) > H) break;
+            const int s = best_fit(J, pool, H, deg, W);
+            if (s < 0) break;
             pool.take(deg[s], s);
             J.add(s, deg);
             remaining -= (long long)deg[s] * deg[s];
@@ -190,7 +300,28 @@ inline bool build_lane_sched(const std::vector<int>& deg, int W, double lscale, 
     std::vector<int> ord(jobs.size());
     for (size_t j = 0; j < ord.size(); ++j) ord[j] = (int)j;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<int> wg_off;
+    if (static_bins) {
+        if (slots > INT32_MAX / 2) return false;
+        const int bins = (int)slots;
+        std::vector<long long> sorted_cost(ord.size());
+        for (size_t j = 0; j < ord.size(); ++j) sorted_cost[j] = cost[ord[j]];
+        const std::vector<int> bin_of = assign_bins(sorted_cost, bins);
+        // group by workgroup, keeping heaviest first inside each
+        std::vector<int> pos(ord.size());
+        for (size_t j = 0; j < pos.size(); ++j) pos[j] = (int)j;
+        std::stable_sort(pos.begin(), pos.end(), [&](int a, int c) {
+            return bin_of[a] != bin_of[c] ? bin_of[a] < bin_of[c] : sorted_cost[a] > sorted_cost[c];
+        });
+        std::vector<int> grouped(ord.size());
+        for (size_t j = 0; j < pos.size(); ++j) grouped[j] = ord[pos[j]];
+        wg_off.assign(bins + 1, 0);
+        for (size_t j = 0; j < pos.size(); ++j) ++wg_off[bin_of[pos[j]] + 1];
+        for (int b = 0; b < bins; ++b) wg_off[b + 1] += wg_off[b];
+        ord.swap(grouped);
+    }
     out = LaneSchedHost{};
+    out.wg_off = wg_off;
     out.njobs = (int)jobs.size();
     out.wave_off.push_back(0);
     out.poly_off.push_back(0);

@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <string>
+#include <thread>
 #include <cstdlib>
 #include <cstdio>
 #include <cmath>
@@ -837,7 +838,9 @@ struct DkLaneSched {
     const int2* lanes;     // per item: 64 (polynomial, root index), polynomial -1 = idle lane
     const int* poly_off;   // njobs + 1: polynomials of job j are polys[poly_off[j] .. poly_off[j+1]-1]
     const int* polys;
+    const int* wg_off;     // static schedule: nbins + 1 job offsets, one range per workgroup; else null
     int njobs;
+    int nbins;             // static schedule: workgroups (the launch's grid); else 0
 };
 
 // One DK update of root idx of polynomial b (b < 0: an idle lane, which loads
@@ -891,18 +894,75 @@ __device__ __forceinline__ void dk_root_lane(const DkPlanDev& P, int b, int idx,
     }
 }
 
-// Lane-packed persistent kernel: W-wave workgroups pull jobs (heaviest
-// first) and sweep their items; the barrier after each sweep orders sweep
-// t's writes before sweep t + 1's reads for every polynomial of the job, and
-// every thread runs the same number of barriers (job index, iters and
-// status are uniform).  The copy-back of an odd sweep count and the status
-// flags go over the job's polynomial list, one polynomial per wave at a time.
+// One job of the lane-packed schedule, swept by a W-wave workgroup: the
+// barrier after each sweep orders sweep t's writes before sweep t + 1's reads
+// for every polynomial of the job, and every thread runs the same number of
+// barriers (slot, iters and status are uniform).  The copy-back of an odd
+// sweep count and the status flags go over the job's polynomial list, one
+// polynomial per wave at a time.
+template <int K, int AR, int W>
+__device__ __forceinline__ void dk_lane_job(const DkPlanDev& P, const DkLaneSched& S, int slot,
+                                            double* rre, double* rim, long long psr,
+                                            int* status, int iters) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int i0 = S.wave_off[slot * W + wv], i1 = S.wave_off[slot * W + wv + 1];
+    for (int it = 0; it < iters; ++it) {
+        const bool from_user = (it & 1) == 0;
+        const double* sre = from_user ? rre : P.zre;
+        const double* sim = from_user ? rim : P.zim;
+        double* dre = from_user ? P.zre : rre;
+        double* dim = from_user ? P.zim : rim;
+        const long long pss = from_user ? psr : P.psz;
+        const long long psd = from_user ? P.psz : psr;
+        for (int i = i0; i < i1; ++i) {
+            const int2 e = S.lanes[64LL * i + lane];
+            dk_root_lane<K, AR>(P, e.x, e.y, S.item_len[i], sre, sim, pss, dre, dim, psd);
+        }
+        __syncthreads();  // iterate t complete before t+1 reads it
+    }
+    const int q0 = S.poly_off[slot], q1 = S.poly_off[slot + 1];
+    if (iters & 1) {  // result is in the plan buffer: copy the job's roots back
+        for (int q = q0 + wv; q < q1; q += W) {
+            const int b = S.polys[q], n = P.degree[b];
+            const long long ro = P.root_off[b];
+            for (int r = lane; r < n; r += 64)
+                c_store<K>(rre, rim, psr, ro + r, c_load<K>(P.zre, P.zim, P.psz, ro + r));
+        }
+        __syncthreads();
+    }
+    if (status) {
+        for (int q = q0 + wv; q < q1; q += W) {
+            const int b = S.polys[q], n = P.degree[b];
+            const long long ro = P.root_off[b];
+            int bad = 0;
+            for (int r = lane; r < n; r += 64) {
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    bad |= !isfinite(rre[c * psr + ro + r]) || !isfinite(rim[c * psr + ro + r]);
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+            if (lane == 0) status[b] = bad;
+        }
+    }
+    __syncthreads();
+}
+
+// Lane-packed persistent kernel.  Dynamic schedule: W-wave workgroups pull
+// jobs (heaviest first) from the plan's counter until none is left.  Static
+// schedule: workgroup g sweeps the jobs wg_off[g] .. wg_off[g+1]-1 (the grid
+// is exactly the schedule's nbins workgroups).
 template <int K, int AR, int W>
 __global__ void __launch_bounds__(64 * W)
 k_dk_lanes(DkPlanDev P, DkLaneSched S, double* rre, double* rim, long long psr, int* status,
            int iters) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    if (S.wg_off) {
+        const int j1 = S.wg_off[blockIdx.x + 1];
+        for (int slot = S.wg_off[blockIdx.x]; slot < j1; ++slot)
+            dk_lane_job<K, AR, W>(P, S, slot, rre, rim, psr, status, iters);
+        return;
+    }
     __shared__ int s_slot;
     for (;;) {
         if (threadIdx.x == 0) s_slot = atomicAdd(P.counter, 1);
@@ -910,47 +970,7 @@ k_dk_lanes(DkPlanDev P, DkLaneSched S, double* rre, double* rim, long long psr, 
         const int slot = s_slot;
         __syncthreads();  // all have read s_slot before it is overwritten
         if (slot >= S.njobs) break;  // the same value in every thread: uniform exit
-        const int i0 = S.wave_off[slot * W + wv], i1 = S.wave_off[slot * W + wv + 1];
-        for (int it = 0; it < iters; ++it) {
-            const bool from_user = (it & 1) == 0;
-            const double* sre = from_user ? rre : P.zre;
-            const double* sim = from_user ? rim : P.zim;
-            double* dre = from_user ? P.zre : rre;
-            double* dim = from_user ? P.zim : rim;
-            const long long pss = from_user ? psr : P.psz;
-            const long long psd = from_user ? P.psz : psr;
-            for (int i = i0; i < i1; ++i) {
-                const int2 e = S.lanes[64LL * i + lane];
-                dk_root_lane<K, AR>(P, e.x, e.y, S.item_len[i], sre, sim, pss, dre, dim, psd);
-            }
-            __syncthreads();  // iterate t complete before t+1 reads it
-        }
-        const int q0 = S.poly_off[slot], q1 = S.poly_off[slot + 1];
-        if (iters & 1) {  // result is in the plan buffer: copy the job's roots back
-            for (int q = q0 + wv; q < q1; q += W) {
-                const int b = S.polys[q], n = P.degree[b];
-                const long long ro = P.root_off[b];
-                for (int r = lane; r < n; r += 64)
-                    c_store<K>(rre, rim, psr, ro + r, c_load<K>(P.zre, P.zim, P.psz, ro + r));
-            }
-            __syncthreads();
-        }
-        if (status) {
-            for (int q = q0 + wv; q < q1; q += W) {
-                const int b = S.polys[q], n = P.degree[b];
-                const long long ro = P.root_off[b];
-                int bad = 0;
-                for (int r = lane; r < n; r += 64) {
-#pragma unroll
-                    for (int c = 0; c < K; ++c)
-                        bad |= !isfinite(rre[c * psr + ro + r]) || !isfinite(rim[c * psr + ro + r]);
-                }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) bad |= __shfl_xor(bad, off, 64);
-                if (lane == 0) status[b] = bad;
-            }
-        }
-        __syncthreads();
+        dk_lane_job<K, AR, W>(P, S, slot, rre, rim, psr, status, iters);
     }
 }
 
@@ -966,24 +986,29 @@ struct DkVariant {
     int w;          // waves per job (DK_LANES)
     int lscale;     // job cap, percent of the largest polynomial's heaviest wave (DK_LANES)
     int sched;      // index of the plan's lane-packed schedule (DK_LANES)
+    int stat;       // 1: static job-to-workgroup schedule (DK_LANES); 0: shared counter
 };
 static const DkVariant kDkVariants[] = {
-    {1, 8, DK_WAVE, 1, 0, -1},    {2, 8, DK_WAVE, 1, 0, -1},    {1, 16, DK_WAVE, 1, 0, -1},
-    {2, 12, DK_WAVE, 1, 0, -1},   {1, 8, DK_PACKED, 4, 0, -1},  {1, 12, DK_PACKED, 4, 0, -1},
-    {1, 12, DK_LANES, 4, 100, 0}, {1, 12, DK_LANES, 4, 150, 1}, {1, 8, DK_LANES, 4, 100, 2},
-    {1, 12, DK_LANES, 12, 200, 3}, {1, 16, DK_LANES, 16, 100, 4}, {1, 16, DK_LANES, 16, 200, 5},
-    {1, 16, DK_LANES, 4, 100, 6}};
+    {1, 8, DK_WAVE, 1, 0, -1, 0},     {2, 8, DK_WAVE, 1, 0, -1, 0},
+    {1, 16, DK_WAVE, 1, 0, -1, 0},    {2, 12, DK_WAVE, 1, 0, -1, 0},
+    {1, 8, DK_PACKED, 4, 0, -1, 0},   {1, 12, DK_PACKED, 4, 0, -1, 0},
+    {1, 12, DK_LANES, 4, 100, 0, 0},  {1, 12, DK_LANES, 4, 150, 1, 0},
+    {1, 8, DK_LANES, 4, 100, 2, 0},   {1, 12, DK_LANES, 12, 200, 3, 0},
+    {1, 16, DK_LANES, 16, 100, 4, 0}, {1, 16, DK_LANES, 16, 200, 5, 0},
+    {1, 16, DK_LANES, 4, 100, 6, 0},  {1, 16, DK_LANES, 16, 100, 7, 1},
+    {1, 12, DK_LANES, 12, 200, 8, 1}, {1, 16, DK_LANES, 16, 200, 9, 1}};
 constexpr int kDkVariantCount = sizeof(kDkVariants) / sizeof(kDkVariants[0]);
-constexpr int kDkLaneScheds = 7;
-// A new plan's variant: lane-packed 16-wave jobs, one per CU (four waves per
-// SIMD).  On 4096 QD polynomials of degrees 16..512 over 200 sweeps it took
-// 3.79 s, against 4.03 s for 12-wave jobs, 4.15 s for the packed 4-wave
-// chunks and 4.3 s for 24 resident waves per CU (12- or 8-wave jobs); the job
-// cap (1 to 2 times the largest polynomial's heaviest wave) moved it by under
-// 2 %.  On 4096 copies of one degree-64 polynomial, where every polynomial is
-// one 64-lane item and 12-wave jobs leave a second round of jobs on a third
-// of the CUs (1.5 times slower), it is within 4 % of the fastest variant.
-constexpr int kDkDefaultVariant = 10;
+constexpr int kDkLaneScheds = 10;
+// A new plan's variant: lane-packed 16-wave jobs (four waves per SIMD) on a
+// static schedule, every CU sweeping its own list of jobs.  On 4096 QD
+// polynomials of degrees 16..512 over 200 sweeps it took 3.57 s, against
+// 3.75 s for the same jobs taken from the shared counter (heaviest first to
+// the first free workgroup leaves some CUs a job short near the end), 3.80 s
+// for 12-wave jobs, 4.15 s for the packed 4-wave chunks and 4.3 s with 24
+// resident waves per CU; the job cap moved it by under 1 %.  On 4096 copies
+// of one degree-64 polynomial (every polynomial one 64-lane item) it is
+// within 3 % of the fastest variant.
+constexpr int kDkDefaultVariant = 13;
 
 }  // namespace mpx
 
@@ -1036,6 +1061,7 @@ static int launch_dk_t(mpx_plan_s* p, const DkVariant& v, const void* are, const
         long long groups = (long long)p->cus * v.waves_cu / W;
         if (groups > S.njobs) groups = S.njobs;
         if (groups < 1) groups = 1;
+        if (S.wg_off) groups = S.nbins;  // one workgroup per range of the static schedule
         k_dk_lanes<K, AR, W><<<(unsigned)groups, 64 * W, 0, s>>>(p->d, S, (double*)rre,
                                                               (double*)rim, psr, status, p->iters);
     } else {
@@ -1484,11 +1510,28 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
             cus = prop.multiProcessorCount;
     }
     // Lane-packed schedules, one per DK_LANES variant (slots: jobs resident at once)
+    // (built side by side, one host thread per schedule)
     LaneSchedHost lsh[kDkLaneScheds];
-    for (const DkVariant& v : kDkVariants) {
-        if (v.kind != DK_LANES) continue;
-        const long long slots = std::max<long long>(1, (long long)cus * v.waves_cu / v.w);
-        if (!build_lane_sched(deg, v.w, v.lscale / 100.0, slots, lsh[v.sched])) return MPX_ENOTSUP;
+    {
+        bool ok[kDkLaneScheds];
+        std::vector<std::thread> th;
+        for (const DkVariant& v : kDkVariants) {
+            if (v.kind != DK_LANES) continue;
+            ok[v.sched] = false;
+            const long long slots = std::max<long long>(1, (long long)cus * v.waves_cu / v.w);
+            auto job = [&deg, &lsh, &ok, v, slots] {
+                ok[v.sched] = build_lane_sched(deg, v.w, v.lscale / 100.0, slots, lsh[v.sched],
+                                               v.stat != 0);
+            };
+            try {
+                th.emplace_back(job);
+            } catch (...) {  // no thread available: build it here
+                job();
+            }
+        }
+        for (std::thread& t : th) t.join();
+        for (const DkVariant& v : kDkVariants)
+            if (v.kind == DK_LANES && !ok[v.sched]) return MPX_ENOTSUP;
     }
 
     auto* p = new (std::nothrow) mpx_plan_s();
@@ -1545,7 +1588,8 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
         const size_t b_wo = h.wave_off.size() * sizeof(int), b_il = std::max<size_t>(h.item_len.size(), 1) * sizeof(int);
         const size_t b_ln = std::max<size_t>(h.lanes.size(), 2) * sizeof(int);
         const size_t b_po = h.poly_off.size() * sizeof(int), b_pl = std::max<size_t>(h.polys.size(), 1) * sizeof(int);
-        if (hipMalloc(&p->lane_dev[i], al(b_wo) + al(b_il) + al(b_ln) + al(b_po) + al(b_pl)) != hipSuccess) {
+        const size_t b_wg = std::max<size_t>(h.wg_off.size(), 1) * sizeof(int);
+        if (hipMalloc(&p->lane_dev[i], al(b_wo) + al(b_il) + al(b_ln) + al(b_po) + al(b_pl) + al(b_wg)) != hipSuccess) {
             mpx_plan_destroy(p);
             return MPX_EDEVICE;
         }
@@ -1555,6 +1599,7 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
         int2* ln = (int2*)take(b_ln);
         int* po = (int*)take(b_po);
         int* pl = (int*)take(b_pl);
+        int* wg = (int*)take(b_wg);
         e = hipMemcpy(wo, h.wave_off.data(), b_wo, hipMemcpyHostToDevice);
         if (e == hipSuccess && !h.item_len.empty())
             e = hipMemcpy(il, h.item_len.data(), h.item_len.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -1563,11 +1608,14 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
         if (e == hipSuccess) e = hipMemcpy(po, h.poly_off.data(), b_po, hipMemcpyHostToDevice);
         if (e == hipSuccess && !h.polys.empty())
             e = hipMemcpy(pl, h.polys.data(), h.polys.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !h.wg_off.empty())
+            e = hipMemcpy(wg, h.wg_off.data(), h.wg_off.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             mpx_plan_destroy(p);
             return MPX_EDEVICE;
         }
-        p->lane[i] = DkLaneSched{wo, il, ln, po, pl, h.njobs};
+        const int nbins = h.wg_off.empty() ? 0 : (int)h.wg_off.size() - 1;
+        p->lane[i] = DkLaneSched{wo, il, ln, po, pl, nbins ? wg : nullptr, h.njobs, nbins};
     }
     *out = p;
     return MPX_OK;

@@ -760,8 +760,14 @@ def main():
         # launches of ~60 ms (2^16 iterations), the engine clock brought to its
         # steady state by 10 untimed launches, median of 5
         r = {k: mpx.probe_valu(k, iters=1 << 16, reps=5, warmup=10) for k in mpx.PROBES}
+        # FP64 additions at low occupancy: fraction of the issue peak for
+        # 1, 2, 4 waves per SIMD and 1..16 independent chains per lane
+        low = {f"{w}_waves_per_simd": {f"{c}_chains": mpx.probe_chains(c, w, iters=(1 << 16) // c)
+                                       / PEAK_F64_ISSUE for c in (1, 2, 4, 8, 16)}
+               for w in (1, 2, 4)}
         print(json.dumps({"peak_probe_lane_ops_per_s": r,
-                          "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE}}), flush=True)
+                          "assumed": {"f64": PEAK_F64_ISSUE, "f32": PEAK_F32_ISSUE},
+                          "f64_add_fraction_low_occupancy": low}), flush=True)
         return
     if args.only:
         fn = {"gemm": lambda: {q: gemm_row(mpx, torch, T, q, args.n) for q in ("qd", "td", "dd", "ff")},

@@ -42,6 +42,30 @@ k_probe_valu(long long iters, T y0, T z0, T* __restrict__ out) {
     out[(long long)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+// How much of the FP64 issue rate few waves reach: NC independent chains of
+// dependent additions per lane, W waves per SIMD (one workgroup of 256 W
+// threads per CU), 8 steps per round.  A lone wave on one chain waits for
+// each result before the next addition can issue; more chains or more waves
+// fill those gaps.
+template <int NC>
+__global__ void __launch_bounds__(1024)
+k_probe_chains(long long iters, double y0, double* __restrict__ out) {
+    const double y = y0 * (double)(1 + (threadIdx.x & 1));
+    double x[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = (double)(threadIdx.x + c);
+    for (long long i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = x[c] + y;
+    }
+    double s = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s = s + x[c];
+    out[(long long)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace mpx
 
 using namespace mpx;
@@ -64,6 +88,30 @@ extern "C" int mpx_probe_valu(int kind, int64_t iters, void* out, int64_t thread
         case MPX_PROBE_F64_FMA: k_probe_valu<double, true><<<grid, 256, 0, s>>>(iters, 1.0, 1e-300, (double*)out); break;
         case MPX_PROBE_F32_ADD: k_probe_valu<float, false><<<grid, 256, 0, s>>>(iters, 1e-30f, 0.0f, (float*)out); break;
         default: k_probe_valu<float, true><<<grid, 256, 0, s>>>(iters, 1.0f, 1e-30f, (float*)out); break;
+    }
+    return launch_status();
+}
+
+extern "C" int64_t mpx_probe_chains_threads(int waves_per_simd) {
+    if (waves_per_simd < 1 || waves_per_simd > 4) return 0;
+    return mpx_probe_threads() / 8 * waves_per_simd;
+}
+
+extern "C" int mpx_probe_chains(int chains, int waves_per_simd, int64_t iters, void* out,
+                                int64_t out_len, void* stream) {
+    const int64_t threads = mpx_probe_chains_threads(waves_per_simd);
+    if (threads <= 0 || iters < 1 || out == nullptr || out_len < threads) return MPX_EINVAL;
+    if (chains != 1 && chains != 2 && chains != 4 && chains != 8 && chains != 16) return MPX_EINVAL;
+    const unsigned block = 256u * (unsigned)waves_per_simd;
+    const unsigned grid = (unsigned)(threads / block);
+    hipStream_t s = as_stream(stream);
+    double* o = (double*)out;
+    switch (chains) {
+        case 1: k_probe_chains<1><<<grid, block, 0, s>>>(iters, 1e-300, o); break;
+        case 2: k_probe_chains<2><<<grid, block, 0, s>>>(iters, 1e-300, o); break;
+        case 4: k_probe_chains<4><<<grid, block, 0, s>>>(iters, 1e-300, o); break;
+        case 8: k_probe_chains<8><<<grid, block, 0, s>>>(iters, 1e-300, o); break;
+        default: k_probe_chains<16><<<grid, block, 0, s>>>(iters, 1e-300, o); break;
     }
     return launch_status();
 }

@@ -80,6 +80,8 @@ def _declare(L):
     sig("mpx_gemm_ozaki_set_variant", _i, _i)
     sig("mpx_probe_threads", _l)
     sig("mpx_probe_valu", _i, _i, _l, _v, _l, _v)
+    sig("mpx_probe_chains_threads", _l, _i)
+    sig("mpx_probe_chains", _i, _i, _i, _l, _v, _l, _v)
     sig("mpx_gemm_batched_plan", _i, C.POINTER(_v), _i, _l, _v, _v, _v)
     sig("mpx_gemm_batched", _i, _v, _v, _l, _v, _l, _v, _l, _v)
     sig("mpx_gemm_batched_variant_count", _i, _v)
@@ -372,6 +374,31 @@ def probe_valu(kind: str, iters: int = 1 << 12, reps: int = 3, warmup: int = 1) 
     torch.cuda.synchronize()
     ms = statistics.median(e0.elapsed_time(e1) for e0, e1 in ev)
     return threads * iters * 64.0 / (ms * 1e-3)
+
+
+def probe_chains(chains: int, waves_per_simd: int, iters: int = 1 << 14, reps: int = 5,
+                 warmup: int = 3) -> float:
+    """FP64 addition rate (lane-operations per second) of `chains`
+    independent dependency chains per lane at `waves_per_simd` waves per SIMD
+    (one workgroup per CU): the median over `reps` launches after `warmup`
+    untimed ones."""
+    import statistics
+    threads = int(lib().mpx_probe_chains_threads(waves_per_simd))
+    if threads <= 0:
+        raise ValueError("waves_per_simd must be 1..4")
+    out = torch.empty(threads, dtype=torch.float64, device="cuda")
+    run = lambda: _check(lib().mpx_probe_chains(chains, waves_per_simd, iters, _ptr(out), threads,
+                                                _stream()), "mpx_probe_chains")
+    for _ in range(warmup):
+        run()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        run()
+        e1.record()
+    torch.cuda.synchronize()
+    ms = statistics.median(e0.elapsed_time(e1) for e0, e1 in ev)
+    return threads * iters * 8.0 * chains / (ms * 1e-3)
 
 
 class GemmBatchPlan:

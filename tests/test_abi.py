@@ -126,6 +126,13 @@ def test_probe_rejects_bad_arguments():
     assert L.mpx_probe_valu(0, 0, FAKE, 256, None) == -1       # iters < 1
     assert L.mpx_probe_valu(0, 1, FAKE, 300, None) == -1       # not a multiple of 256
     assert L.mpx_probe_valu(0, 1, None, 256, None) == -1       # null output
+    assert L.mpx_probe_chains_threads(0) == 0 and L.mpx_probe_chains_threads(5) == 0
+    big = 1 << 40
+    assert L.mpx_probe_chains(3, 1, 1, FAKE, big, None) == -1     # chains not a power of two <= 16
+    assert L.mpx_probe_chains(4, 0, 1, FAKE, big, None) == -1     # waves per SIMD outside 1..4
+    assert L.mpx_probe_chains(4, 1, 0, FAKE, big, None) == -1     # iters < 1
+    assert L.mpx_probe_chains(4, 1, 1, None, big, None) == -1     # null output
+    assert L.mpx_probe_chains(4, 1, 1, FAKE, 1, None) == -1       # output too short
 
 
 def test_strides_whose_span_overflows_int64_rejected():

@@ -284,7 +284,10 @@ static const std::vector<Variant>& variants(int prec) {
                                             {run_variant<double, 2, 1, 2, 16, AR_BF, true>, 16, 32, "dd_1x2_k16_pf"},
                                             {run_variant<double, 2, 1, 1, 16, AR_BF, true>, 16, 16, "dd_1x1_k16_pf"},
                                             {run_variant<double, 2, 2, 2, 16, AR_BF, true>, 32, 32, "dd_2x2_k16_pf"},
-                                            {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"}};
+                                            {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"},
+                                            {run_variant<double, 2, 2, 2, 32, AR_BF, true>, 32, 32, "dd_2x2_k32_pf"},
+                                            {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
+                                            {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
                                             {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},
                                             {run_variant<double, 3, 1, 1, 16, AR_BF, true>, 16, 16, "td_1x1_k16_pf"},

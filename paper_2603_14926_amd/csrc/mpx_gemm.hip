@@ -278,7 +278,13 @@ struct Variant {
 static const std::vector<Variant>& variants(int prec) {
     // DD also offers 16 x 32 and 16 x 16 tiles: at n = 512 the 32 x 32 tile
     // leaves one workgroup per CU
-    static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd"),
+    // (the 2 x 4 tile with a 16-deep prefetched panel comes before the other
+    // 32 x 64 tilings: the size heuristic takes the first of equal areas, and
+    // it is the fastest DD tiling at 2048)
+    static const std::vector<Variant> dd = {{run_variant<double, 2, 4, 4, 8, AR_BF>, 64, 64, "dd_4x4_k8"},
+                                            {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
+                                            {run_variant<double, 2, 2, 4, 8, AR_BF>, 32, 64, "dd_2x4_k8"},
+                                            {run_variant<double, 2, 2, 2, 16, AR_BF>, 32, 32, "dd_2x2_k16"},
                                             {run_variant<double, 2, 1, 2, 16, AR_BF>, 16, 32, "dd_1x2_k16"},
                                             {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"},
                                             {run_variant<double, 2, 1, 2, 16, AR_BF, true>, 16, 32, "dd_1x2_k16_pf"},
@@ -286,7 +292,6 @@ static const std::vector<Variant>& variants(int prec) {
                                             {run_variant<double, 2, 2, 2, 16, AR_BF, true>, 32, 32, "dd_2x2_k16_pf"},
                                             {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"},
                                             {run_variant<double, 2, 2, 2, 32, AR_BF, true>, 32, 32, "dd_2x2_k32_pf"},
-                                            {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
                                             {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
                                             {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},

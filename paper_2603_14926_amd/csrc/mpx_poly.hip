@@ -1520,8 +1520,12 @@ static int polyroots_plan(mpx_plan* out, int prec, int64_t batch, const int32_t*
             ok[v.sched] = false;
             const long long slots = std::max<long long>(1, (long long)cus * v.waves_cu / v.w);
             auto job = [&deg, &lsh, &ok, v, slots] {
-                ok[v.sched] = build_lane_sched(deg, v.w, v.lscale / 100.0, slots, lsh[v.sched],
-                                               v.stat != 0);
+                try {
+                    ok[v.sched] = build_lane_sched(deg, v.w, v.lscale / 100.0, slots,
+                                                   lsh[v.sched], v.stat != 0);
+                } catch (...) {  // out of host memory: the plan fails, the process goes on
+                    ok[v.sched] = false;
+                }
             };
             try {
                 th.emplace_back(job);

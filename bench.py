@@ -102,12 +102,14 @@ class Timer:
         return float(np.median([e0.elapsed_time(e1) / reps for e0, e1 in ev]))
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the headline GEMM kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE, each scaled by the
-    same counter on a copy kernel of known size), or None when the summary is
-    missing, is for another workload, or was taken on different kernel
-    sources (SHA-256 prefix of the sources recorded with the counters)."""
+def measured_traffic(workload: str, tiling: str):
+    """HBM bytes per launch of the headline GEMM kernel in the given tiling
+    from the committed rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE,
+    each scaled by the same counter on a copy kernel of known size; the
+    counter runs autotune, so every tiling of the size is counted), or None
+    when the summary is missing, is for another workload, lacks the tiling,
+    or was taken on different kernel sources (SHA-256 prefix of the sources
+    recorded with the counters)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
     if not os.path.exists(path):
@@ -120,7 +122,7 @@ def measured_traffic(workload: str):
             h.update(fh.read())
     if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    return rec["traffic_bytes"]
+    return rec.get("traffic_bytes_by_tiling", {}).get(tiling)
 
 
 def log(msg):
@@ -831,7 +833,7 @@ def main():
             "unit": "T FP64 VALU lane-instructions/s" if p != "ff" else "T FP32 VALU lane-instructions/s",
             "frac": achieved / peak,
             "frac_fp64_flop_peak": macs * FLOP_PER_MAC[p] / (ms * 1e-3) / PEAK_F64_FLOP,
-            "traffic": measured_traffic(f"{p}_gemm_{n}") if variant == 0 else None,
+            "traffic": measured_traffic(f"{p}_gemm_{n}", mpx.gemm_variants(p)[variant]),
             "traffic_unit": "bytes per launch (HBM fetch + write, rocprofv3 counters scaled by a copy kernel)",
             "algorithmic_bytes": 3.0 * K * (4 if p == "ff" else 8) * n * n,
         },

@@ -42,8 +42,12 @@ def test_traffic_only_from_counters_on_current_sources(tmp_path):
     assert "paper_2603_14926_amd/csrc/mpx_gemm.hip" in rec["sources"]
     # the tree itself: the recorded figure exactly when the sources match
     fresh = _sources_hash(ROOT, rec["sources"]) == rec["source_sha256_16"]
-    assert bench.measured_traffic("qd_gemm_2048") == (rec["traffic_bytes"] if fresh else None)
-    assert bench.measured_traffic("no_such_workload") is None
+    by = rec["traffic_bytes_by_tiling"]
+    assert by[rec["tiling"]] == rec["traffic_bytes"]
+    for name, t in by.items():
+        assert bench.measured_traffic("qd_gemm_2048", name) == (t if fresh else None)
+    assert bench.measured_traffic("qd_gemm_2048", "no_such_tiling") is None
+    assert bench.measured_traffic("no_such_workload", rec["tiling"]) is None
     # a copy whose record matches its sources, then one byte changed: no traffic
     os.makedirs(tmp_path / "profiles")
     for f in rec["sources"]:
@@ -54,10 +58,10 @@ def test_traffic_only_from_counters_on_current_sources(tmp_path):
     with open(tmp_path / "profiles" / "qd_gemm_2048_counters.json", "w") as fh:
         json.dump(rec2, fh)
     bench.ROOT = str(tmp_path)
-    assert bench.measured_traffic("qd_gemm_2048") == rec["traffic_bytes"]
+    assert bench.measured_traffic("qd_gemm_2048", rec["tiling"]) == rec["traffic_bytes"]
     with open(tmp_path / rec["sources"][0], "ab") as fh:
         fh.write(b"\n")
-    assert bench.measured_traffic("qd_gemm_2048") is None
+    assert bench.measured_traffic("qd_gemm_2048", rec["tiling"]) is None
 
 
 def test_cpu_baseline_fields():

@@ -77,18 +77,25 @@ def parse():
 
 
 class Timer:
-    """Median time per call (ms): `warmup` untimed calls, then `samples`
-    samples, each the HIP-event time of `reps` back-to-back calls on the
-    current stream divided by `reps` (reps > 1 only for calls of a few
-    microseconds, where one event pair per call would dominate)."""
+    """Median time per call (ms): untimed calls (at least `warmup`, and more
+    until about `warm_s` seconds have passed: the engine clock ramps up over
+    tens of milliseconds of sustained work, and a DD GEMM of a millisecond
+    runs up to 25 % slower in its first calls after an idle spell), then
+    `samples` samples, each the HIP-event time of `reps` back-to-back calls
+    on the current stream divided by `reps` (reps > 1 only for calls of a
+    few microseconds, where one event pair per call would dominate)."""
 
     def __init__(self, torch):
         self.torch = torch
 
-    def __call__(self, fn, reps=1, samples=10, warmup=3):
+    def __call__(self, fn, reps=1, samples=10, warmup=3, warm_s=0.1):
         torch = self.torch
-        for _ in range(warmup):
+        t0, i = time.perf_counter(), 0
+        while i < warmup or time.perf_counter() - t0 < warm_s:
             fn()
+            i += 1
+            if i % 8 == 0:
+                torch.cuda.synchronize()  # keep the host from running ahead of the GPU
         torch.cuda.synchronize()
         s = torch.cuda.current_stream()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -27,6 +27,10 @@
 // Workgroups are numbered so that each of the eight XCDs (which receive
 // workgroups round-robin) works on compact blocks of tiles whose A and B
 // panels stay in its L2.
+//
+// For small products a second kernel, k_gemm_rw, gives each wave whole rows
+// of C (A through scalar loads, B straight from global memory, no LDS and no
+// barriers); it is described where it is defined.
 #include "mp_arith.hpp"
 #include "mp_conv.hpp"
 #include "mpx_internal.hpp"
@@ -223,6 +227,151 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
                                                 n0, sA, sB);
 }
 
+// Row-wave tiling, for products too small to give every SIMD several waves of
+// the LDS-tiled kernel: each wave64 owns R rows x 64 columns of C, one column
+// per lane, so at every step all lanes of a wave multiply by the same A
+// entries.  Those are read with scalar loads into scalar registers (one copy
+// per wave, no LDS traffic), and each lane loads its own B entry from global
+// memory at a wave-uniform base plus a 32-bit per-lane byte offset (64
+// consecutive doubles per component when B is not transposed; the four waves
+// of a workgroup read the same B columns, which the vector L1 cache shares).
+// With no LDS there are no barriers: every wave runs its R multiply-add chains
+// on its own.  Panels of BK steps alternate between two register buffers;
+// the next panel's loads are issued after the first step of the current one
+// (so the wait for the current panel's scalar loads, which return out of
+// order and are waited for all at once, comes before them) and overlap the
+// remaining steps.  Each C_ij is still accumulated in ascending l from zero
+// with the same operation, so the bits equal those of every other tiling.
+// The launcher checks that the per-lane byte offsets fit in 32 bits.
+// Raw buffer loads: word 3 of a gfx9 buffer resource with a 32-bit data
+// format and no swizzle; the range is left unlimited (the launcher bounds
+// every offset).
+constexpr int kBufWord3 = 0x00020000;
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+
+template <typename T, int K, int R, int BK, bool TA, bool TB, int AR>
+__global__ void __launch_bounds__(kGemmThreads)
+k_gemm_rw(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,
+          const T* __restrict__ B, long long ldb, long long psB, T* __restrict__ C,
+          long long ldc, long long psC, int groups_n) {
+    constexpr int WAVES = kGemmThreads / 64;
+    const int lane = threadIdx.x & 63;
+    // workgroup = WAVES consecutive row blocks of one 64-column group; the
+    // wave index is made explicitly uniform so the A addresses are scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int cg = blockIdx.x % groups_n;
+    const int r0 = ((blockIdx.x / groups_n) * WAVES + w) * R;
+    if (r0 >= m) return;
+    const int j = cg * 64 + lane;
+    const int jl = j < n ? j : n - 1;  // loads stay inside B; results of j >= n are dropped
+    const unsigned boff = (unsigned)((TB ? (long long)jl * ldb : (long long)jl) * (long long)sizeof(T));
+    int rows[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) rows[i] = r0 + i < m ? r0 + i : m - 1;
+
+    mpn<T, K> acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = mp_zero<T, K>();
+
+    auto a_at = [&](int i, int l, int c) -> T {
+        return A[c * psA + (TA ? (long long)l * lda + rows[i] : (long long)rows[i] * lda + l)];
+    };
+    // B entries (l .. l + BK - 1, column j) of component c: a buffer resource
+    // at the wave-uniform address of entry (l, column 0), the lane's byte
+    // offset, and a uniform byte offset per step
+    const int bstep = (int)((TB ? 1LL : ldb) * (long long)sizeof(T));
+    auto b_rsrc = [&](int l, int c) {
+        const T* base = B + c * psB + (TB ? (long long)l : (long long)l * ldb);
+        return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, kBufWord3);
+    };
+    auto b_at = [&](int l, int c) -> T { return buf_load<T>(b_rsrc(l, c), boff, 0); };
+    using PanelA = T[R][BK][K];
+    using PanelB = T[BK][K];
+    auto load = [&](int k0, PanelA& a, PanelB& b) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const auto rs = b_rsrc(k0, c);
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk) b[kk][c] = buf_load<T>(rs, boff, kk * bstep);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk)
+#pragma unroll
+                for (int c = 0; c < K; ++c) a[i][kk][c] = a_at(i, k0 + kk, c);
+    };
+    auto step = [&](const PanelA& a, const PanelB& b, int kk) {
+        mpn<T, K> bv;
+#pragma unroll
+        for (int c = 0; c < K; ++c) bv.c[c] = b[kk][c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            mpn<T, K> av;
+#pragma unroll
+            for (int c = 0; c < K; ++c) av.c[c] = a[i][kk][c];
+            acc[i] = ar_add<AR>(acc[i], ar_mul<AR>(av, bv));
+        }
+    };
+    auto consume = [&](const PanelA& a, const PanelB& b) {
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) step(a, b, kk);
+    };
+    // consume (a, b) while loading the panel at k0 into (na, nb)
+    auto consume_next = [&](const PanelA& a, const PanelB& b, int k0, PanelA& na, PanelB& nb) {
+        step(a, b, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(k0, na, nb);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int kk = 1; kk < BK; ++kk) step(a, b, kk);
+    };
+
+    const int npan = k / BK;
+    if (npan > 0) {
+        T ax[R][BK][K], bx[BK][K], ay[R][BK][K], by[BK][K];
+        load(0, ax, bx);
+        int p = 0;
+        for (; p + 2 <= npan; p += 2) {  // panel p is in x
+            consume_next(ax, bx, (p + 1) * BK, ay, by);
+            if (p + 2 < npan) consume_next(ay, by, (p + 2) * BK, ax, bx);
+            else consume(ay, by);
+        }
+        if (p < npan) consume(ax, bx);
+    }
+    for (int l = npan * BK; l < k; ++l) {
+        T a1[R][1][K], b1[1][K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) b1[0][c] = b_at(l, c);
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int c = 0; c < K; ++c) a1[i][0][c] = a_at(i, l, c);
+        mpn<T, K> bv;
+#pragma unroll
+        for (int c = 0; c < K; ++c) bv.c[c] = b1[0][c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            mpn<T, K> av;
+#pragma unroll
+            for (int c = 0; c < K; ++c) av.c[c] = a1[i][0][c];
+            acc[i] = ar_add<AR>(acc[i], ar_mul<AR>(av, bv));
+        }
+    }
+
+    if (j < n) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (r0 + i < m) mp_store<T, K>(C, psC, (long long)(r0 + i) * ldc + j, acc[i]);
+    }
+}
+
 // ----------------------------------------------------------- variants ----
 
 struct GemmArgs {
@@ -244,6 +393,33 @@ static int run_variant(const GemmArgs& g, hipStream_t s) {
     k_gemm<T, K, TM, TN, BK, TA_, TB_, AR, PF><<<total, kGemmThreads, 0, s>>>(              \
         g.m, g.n, g.k, (const T*)g.A, g.lda, g.psA, (const T*)g.B, g.ldb, g.psB, (T*)g.C,   \
         g.ldc, g.psC, tn, total)
+    if (!g.tA && !g.tB) MPX_GEMM_LAUNCH(false, false);
+    else if (g.tA && !g.tB) MPX_GEMM_LAUNCH(true, false);
+    else if (!g.tA && g.tB) MPX_GEMM_LAUNCH(false, true);
+    else MPX_GEMM_LAUNCH(true, true);
+#undef MPX_GEMM_LAUNCH
+    return launch_status();
+}
+
+// The row-wave kernel addresses B with 32-bit byte offsets from a panel's
+// first row (or column); where they would not fit, the LDS-tiled 16 x 16 tiling runs instead (same
+// operations in the same order, so the same bits).
+template <typename T, int K, int R, int BK, int AR>
+static int run_variant_rw(const GemmArgs& g, hipStream_t s) {
+    constexpr int WAVES = kGemmThreads / 64;
+    // lane offset + step offset, in bytes, of the farthest B entry of a panel
+    const long long lane_off = g.n <= 0 ? 0 : (g.tB ? (long long)(g.n - 1) * g.ldb : (long long)(g.n - 1));
+    const long long step_off = (long long)(BK - 1) * (g.tB ? 1LL : g.ldb);
+    if ((lane_off + step_off + 1) * (long long)sizeof(T) > (long long)INT32_MAX)
+        return run_variant<T, K, 1, 1, 16, AR, true>(g, s);
+    const long long groups_n = ceil_div(g.n, 64);
+    const long long wgs = groups_n * ceil_div(g.m, (long long)WAVES * R);
+    if (wgs > INT32_MAX / 2) return MPX_ENOTSUP;
+    if (wgs == 0) return MPX_OK;
+#define MPX_GEMM_LAUNCH(TA_, TB_)                                                              \
+    k_gemm_rw<T, K, R, BK, TA_, TB_, AR><<<(int)wgs, kGemmThreads, 0, s>>>(                    \
+        g.m, g.n, g.k, (const T*)g.A, g.lda, g.psA, (const T*)g.B, g.ldb, g.psB, (T*)g.C,      \
+        g.ldc, g.psC, (int)groups_n)
     if (!g.tA && !g.tB) MPX_GEMM_LAUNCH(false, false);
     else if (g.tA && !g.tB) MPX_GEMM_LAUNCH(true, false);
     else if (!g.tA && g.tB) MPX_GEMM_LAUNCH(false, true);
@@ -280,7 +456,9 @@ static const std::vector<Variant>& variants(int prec) {
     // leaves one workgroup per CU
     // (the 2 x 4 tile with a 16-deep prefetched panel comes before the other
     // 32 x 64 tilings: the size heuristic takes the first of equal areas, and
-    // it is the fastest DD tiling at 2048)
+    // it is the fastest DD tiling at 2048).  The row-wave tilings ("rw", a
+    // workgroup of 4R x 64) come last, so the untuned heuristic keeps the LDS
+    // tilings; the autotuner picks them where they win (n = 512 and 1024).
     static const std::vector<Variant> dd = {{run_variant<double, 2, 4, 4, 8, AR_BF>, 64, 64, "dd_4x4_k8"},
                                             {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
                                             {run_variant<double, 2, 2, 4, 8, AR_BF>, 32, 64, "dd_2x4_k8"},
@@ -292,16 +470,21 @@ static const std::vector<Variant>& variants(int prec) {
                                             {run_variant<double, 2, 2, 2, 16, AR_BF, true>, 32, 32, "dd_2x2_k16_pf"},
                                             {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"},
                                             {run_variant<double, 2, 2, 2, 32, AR_BF, true>, 32, 32, "dd_2x2_k32_pf"},
-                                            {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"}};
+                                            {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"},
+                                            {run_variant_rw<double, 2, 1, 4, AR_BF>, 4, 64, "dd_rw1_k4"},
+                                            {run_variant_rw<double, 2, 2, 2, AR_BF>, 8, 64, "dd_rw2_k2"}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
                                             {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},
                                             {run_variant<double, 3, 1, 1, 16, AR_BF, true>, 16, 16, "td_1x1_k16_pf"},
                                             {run_variant<double, 3, 1, 2, 16, AR_BF, true>, 16, 32, "td_1x2_k16_pf"},
-                                            {run_variant<double, 3, 2, 2, 8, AR_BF, true>, 32, 32, "td_2x2_k8_pf"}};
+                                            {run_variant<double, 3, 2, 2, 8, AR_BF, true>, 32, 32, "td_2x2_k8_pf"},
+                                            {run_variant_rw<double, 3, 1, 4, AR_BF>, 4, 64, "td_rw1_k4"},
+                                            {run_variant_rw<double, 3, 2, 2, AR_BF>, 8, 64, "td_rw2_k2"}};
     static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd"),
                                             {run_variant<double, 4, 1, 1, 16, AR_BF, true>, 16, 16, "qd_1x1_k16_pf"},
                                             {run_variant<double, 4, 1, 2, 16, AR_BF, true>, 16, 32, "qd_1x2_k16_pf"},
-                                            {run_variant<double, 4, 2, 2, 8, AR_BF, true>, 32, 32, "qd_2x2_k8_pf"}};
+                                            {run_variant<double, 4, 2, 2, 8, AR_BF, true>, 32, 32, "qd_2x2_k8_pf"},
+                                            {run_variant_rw<double, 4, 1, 2, AR_BF>, 4, 64, "qd_rw1_k2"}};
     static const std::vector<Variant> ff = {
         {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},
         {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},
@@ -311,6 +494,8 @@ static const std::vector<Variant>& variants(int prec) {
         {run_variant<float, 2, 2, 4, 8, AR_BF, true>, 32, 64, "ff_2x4_k8_pf"},
         {run_variant<float, 2, 2, 2, 16, AR_BF, true>, 32, 32, "ff_2x2_k16_pf"},
         {run_variant<float, 2, 1, 1, 16, AR_BF, true>, 16, 16, "ff_1x1_k16_pf"},
+        {run_variant_rw<float, 2, 1, 8, AR_BF>, 4, 64, "ff_rw1_k8"},
+        {run_variant_rw<float, 2, 2, 4, AR_BF>, 8, 64, "ff_rw2_k4"},
     };
     static const std::vector<Variant> dd_nobf = {MPX_TILES_DD(AR_NOBF, "dd_nobf")};
     static const std::vector<Variant> td_nobf = {MPX_TILES_TD(AR_NOBF, "td_nobf")};
@@ -477,6 +662,8 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
     EventPair ev;
     if (!ev.ok) return MPX_EDEVICE;
     const auto& vs = variants(prec);
+    const int v0 = default_variant(prec, g);
+    st = warm_clock(ev, s, [&] { return vs[v0].fn(g, s); });
     int best = -1;
     float best_t = 0.f;
     for (int round = 0; round < 2 && !st; ++round)
@@ -889,6 +1076,7 @@ extern "C" int mpx_gemm_batched_autotune(mpx_gemm_plan p, const void* A, int64_t
     hipStream_t s = mpx::as_stream(stream);
     mpx::EventPair ev;
     if (!ev.ok) return MPX_EDEVICE;
+    st = mpx::warm_clock(ev, s, [&] { return gb_run(p, p->variant, A, psA, B, psB, C, psC, s); });
     int best = -1;
     float best_t = 0.f;
     // two rounds over all variants, each variant's faster round counts (as

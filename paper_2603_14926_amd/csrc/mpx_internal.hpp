@@ -102,6 +102,27 @@ struct EventPair {
     }
 };
 
+// The engine clock ramps up over tens of milliseconds of sustained work (a
+// DD GEMM of about a millisecond runs up to 25 % slower in its first calls
+// after an idle spell than after thirty calls in a row), so an autotuner
+// first runs the operation for about kTuneWarmMs of GPU time (at most
+// kTuneWarmCalls calls) and only then times the candidates; otherwise the
+// first candidates are timed at a lower clock than the last.
+constexpr float kTuneWarmMs = 100.f;
+constexpr int kTuneWarmCalls = 4096;
+template <typename F>
+int warm_clock(EventPair& ev, hipStream_t s, F run_once) {
+    float total = 0.f;
+    for (int calls = 0; total < kTuneWarmMs && calls < kTuneWarmCalls; ++calls) {
+        if (!ev.start(s)) return MPX_EDEVICE;
+        if (int st = run_once()) return st;
+        float ms = 0.f;
+        if (!ev.stop(s) || !ev.elapsed(&ms)) return MPX_EDEVICE;
+        total += ms;
+    }
+    return MPX_OK;
+}
+
 }  // namespace mpx
 
 namespace mpx {

@@ -1739,17 +1739,26 @@ extern "C" int mpx_polyroots_autotune(mpx_plan p, const void* coef_re, const voi
     p->flags &= ~(unsigned)MPX_DK_INIT;
     float t[kDkVariantCount];
     for (int v = 0; v < kDkVariantCount; ++v) t[v] = -1.f;
-    // two rounds over all variants, each variant's faster round counts (the
-    // engine clock may still be ramping up during the first)
+    // every trial starts from a copy of the caller's roots
+    auto copy_in = [&]() {
+        for (int c = 0; c < p->K; ++c)
+            if (hipMemcpyAsync(tre + (size_t)c * p->total_roots, (const double*)roots_re + (size_t)c * psr,
+                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(tim + (size_t)c * p->total_roots, (const double*)roots_im + (size_t)c * psr,
+                               plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return (int)MPX_EDEVICE;
+        return (int)MPX_OK;
+    };
+    // the engine clock ramps up under load: run the current variant first
+    st = copy_in();
+    if (!st)
+        st = warm_clock(ev, s, [&] {
+            return launch_dk(p, p->variant, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);
+        });
+    // two rounds over all variants, each variant's faster round counts
     for (int round = 0; round < 2 && !st; ++round)
         for (int v = 0; v < kDkVariantCount && !st; ++v) {
-            for (int c = 0; c < p->K && !st; ++c) {
-                if (hipMemcpyAsync(tre + (size_t)c * p->total_roots, (const double*)roots_re + (size_t)c * psr,
-                                   plane, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                    hipMemcpyAsync(tim + (size_t)c * p->total_roots, (const double*)roots_im + (size_t)c * psr,
-                                   plane, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                    st = MPX_EDEVICE;
-            }
+            st = copy_in();
             if (st) break;
             if (!ev.start(s)) { st = MPX_EDEVICE; break; }
             st = launch_dk(p, v, coef_re, coef_im, psc, tre, tim, p->total_roots, nullptr, s);

@@ -224,7 +224,8 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
  * kernel) on the stream, allocates nothing and may be captured in a HIP
  * graph; calls that overlap on one plan race on its counter.
  * mpx_gemm_batched_autotune times each tiling on the caller's buffers (C is
- * overwritten) in two rounds over all tilings (a tiling's time is its faster
+ * overwritten), after about 100 ms of warm-up calls of the plan's current
+ * tiling, in two rounds over all tilings (a tiling's time is its faster
  * round), keeps the fastest in the plan and returns its index (it
  * synchronises the stream).  Errors as for mpx_gemm; the constructor also
  * returns MPX_ENOTSUP when a tiling's work list would pass 2^30 items and
@@ -268,9 +269,11 @@ int mpx_gemm_variant(int prec, int variant, int transA, int transB, int64_t m, i
                      int64_t ldb, int64_t psB, void *C, int64_t ldc, int64_t psC,
                      void *stream);
 /* Time every variant `reps` times on the given buffers (C is overwritten)
- * with HIP events on `stream`, in two rounds over all variants (a variant's
- * time is its faster round, so an engine clock still ramping up during the
- * first round does not favour the variants timed last), remember the fastest
+ * with HIP events on `stream`, after about 100 ms of warm-up calls (the
+ * engine clock ramps up over tens of milliseconds of sustained work), in two
+ * rounds over all variants (a variant's time is its faster round), skipping
+ * the row-wave tilings ("_rw" names) for products with 4096 or more tiles of
+ * 32 x 32, where they re-read B far more and run no faster; remember the fastest
  * for this bucket and return its index (>= 0) or a negative status; *best_ms
  * (nullable) receives its mean time per call.  Synchronises `stream`; must not be called under graph
  * capture. */
@@ -421,7 +424,8 @@ int mpx_plan_destroy(mpx_plan plan);
  * jobs (four waves per SIMD) on the static assignment, or the variant the
  * tune cache holds for its (precision, batch, largest degree) bucket, or
  * MPX_DK_VARIANT (see the GEMM tuning notes).  The autotuner runs each for
- * iters_probe sweeps on a private copy of the given start roots, in two
+ * iters_probe sweeps on a private copy of the given start roots, after
+ * about 100 ms of warm-up runs of the plan's current variant, in two
  * rounds over all variants (a variant's time is its faster round), switches
  * the plan to the fastest only when it beats the plan's current variant by
  * at least 3 %, and returns the index kept (or a negative status), which it

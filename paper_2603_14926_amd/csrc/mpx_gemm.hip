@@ -434,7 +434,16 @@ struct Variant {
     VariantFn fn;
     int bm, bn;
     const char* name;
+    bool small_only = false;  // autotuned only for small products
 };
+
+// The row-wave tilings re-read a whole B column strip for every 4R rows of C
+// (at 2048^3 in QD that is about 70 GB of L2 reads and 10.9 GB of HBM traffic
+// per launch, against 16 GB and 3.4 GB for the 32 x 32 LDS tiling), and they
+// run no faster there.  They pay off where the LDS tilings leave the SIMDs
+// with few waves, so the autotuner tries them only for products with fewer
+// than 4096 tiles of 32 x 32 (16 per CU).
+static bool small_product(const GemmArgs& g) { return ceil_div(g.m, 32) * ceil_div(g.n, 32) < 4096; }
 
 // Candidate micro-tiles per precision and arithmetic (index 0 = largest
 // tile).  The conventional lists mirror the branch-free ones.
@@ -458,7 +467,8 @@ static const std::vector<Variant>& variants(int prec) {
     // 32 x 64 tilings: the size heuristic takes the first of equal areas, and
     // it is the fastest DD tiling at 2048).  The row-wave tilings ("rw", a
     // workgroup of 4R x 64) come last, so the untuned heuristic keeps the LDS
-    // tilings; the autotuner picks them where they win (n = 512 and 1024).
+    // tilings; the autotuner tries them for small products (small_product)
+    // and picks them where they win (n = 512 and 1024).
     static const std::vector<Variant> dd = {{run_variant<double, 2, 4, 4, 8, AR_BF>, 64, 64, "dd_4x4_k8"},
                                             {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
                                             {run_variant<double, 2, 2, 4, 8, AR_BF>, 32, 64, "dd_2x4_k8"},
@@ -471,20 +481,20 @@ static const std::vector<Variant>& variants(int prec) {
                                             {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"},
                                             {run_variant<double, 2, 2, 2, 32, AR_BF, true>, 32, 32, "dd_2x2_k32_pf"},
                                             {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"},
-                                            {run_variant_rw<double, 2, 1, 4, AR_BF>, 4, 64, "dd_rw1_k4"},
-                                            {run_variant_rw<double, 2, 2, 2, AR_BF>, 8, 64, "dd_rw2_k2"}};
+                                            {run_variant_rw<double, 2, 1, 4, AR_BF>, 4, 64, "dd_rw1_k4", true},
+                                            {run_variant_rw<double, 2, 2, 2, AR_BF>, 8, 64, "dd_rw2_k2", true}};
     static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
                                             {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},
                                             {run_variant<double, 3, 1, 1, 16, AR_BF, true>, 16, 16, "td_1x1_k16_pf"},
                                             {run_variant<double, 3, 1, 2, 16, AR_BF, true>, 16, 32, "td_1x2_k16_pf"},
                                             {run_variant<double, 3, 2, 2, 8, AR_BF, true>, 32, 32, "td_2x2_k8_pf"},
-                                            {run_variant_rw<double, 3, 1, 4, AR_BF>, 4, 64, "td_rw1_k4"},
-                                            {run_variant_rw<double, 3, 2, 2, AR_BF>, 8, 64, "td_rw2_k2"}};
+                                            {run_variant_rw<double, 3, 1, 4, AR_BF>, 4, 64, "td_rw1_k4", true},
+                                            {run_variant_rw<double, 3, 2, 2, AR_BF>, 8, 64, "td_rw2_k2", true}};
     static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd"),
                                             {run_variant<double, 4, 1, 1, 16, AR_BF, true>, 16, 16, "qd_1x1_k16_pf"},
                                             {run_variant<double, 4, 1, 2, 16, AR_BF, true>, 16, 32, "qd_1x2_k16_pf"},
                                             {run_variant<double, 4, 2, 2, 8, AR_BF, true>, 32, 32, "qd_2x2_k8_pf"},
-                                            {run_variant_rw<double, 4, 1, 2, AR_BF>, 4, 64, "qd_rw1_k2"}};
+                                            {run_variant_rw<double, 4, 1, 2, AR_BF>, 4, 64, "qd_rw1_k2", true}};
     static const std::vector<Variant> ff = {
         {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},
         {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},
@@ -494,8 +504,8 @@ static const std::vector<Variant>& variants(int prec) {
         {run_variant<float, 2, 2, 4, 8, AR_BF, true>, 32, 64, "ff_2x4_k8_pf"},
         {run_variant<float, 2, 2, 2, 16, AR_BF, true>, 32, 32, "ff_2x2_k16_pf"},
         {run_variant<float, 2, 1, 1, 16, AR_BF, true>, 16, 16, "ff_1x1_k16_pf"},
-        {run_variant_rw<float, 2, 1, 8, AR_BF>, 4, 64, "ff_rw1_k8"},
-        {run_variant_rw<float, 2, 2, 4, AR_BF>, 8, 64, "ff_rw2_k4"},
+        {run_variant_rw<float, 2, 1, 8, AR_BF>, 4, 64, "ff_rw1_k8", true},
+        {run_variant_rw<float, 2, 2, 4, AR_BF>, 8, 64, "ff_rw2_k4", true},
     };
     static const std::vector<Variant> dd_nobf = {MPX_TILES_DD(AR_NOBF, "dd_nobf")};
     static const std::vector<Variant> td_nobf = {MPX_TILES_TD(AR_NOBF, "td_nobf")};
@@ -666,8 +676,10 @@ extern "C" int mpx_gemm_autotune(int prec, int transA, int transB, int64_t m, in
     st = warm_clock(ev, s, [&] { return vs[v0].fn(g, s); });
     int best = -1;
     float best_t = 0.f;
+    const bool small = small_product(g);
     for (int round = 0; round < 2 && !st; ++round)
         for (int v = 0; v < (int)vs.size(); ++v) {
+            if (vs[v].small_only && !small) continue;
             if (!ev.start(s)) { st = MPX_EDEVICE; break; }
             for (int r = 0; r < reps && !st; ++r) st = vs[v].fn(g, s);
             float ms = 0.f;

@@ -68,3 +68,21 @@ def test_dk_plan_uses_cached_and_forced_variant(cache):
     assert mpx.RootsPlan("qd", deg, iters=2, init=False, graph=False).variant() == other
     mp.setenv("MPX_DK_VARIANT", "1")
     assert mpx.RootsPlan("qd", deg, iters=2, init=False, graph=False).variant() == 1
+
+
+def test_gemm_autotune_keeps_row_wave_tilings_to_small_products(cache):
+    """A product with 64 x 64 tiles of 32 x 32 (4096, the limit) is not given
+    to a row-wave tiling ("_rw"), which re-reads B for every few rows; the
+    picked tiling still gives the same bits as the row-wave ones."""
+    L, _, _ = cache
+    m = n = 2048
+    A = to_gpu(synth.mp_array(2, (m, 16), 5, "U"))
+    B = to_gpu(synth.mp_array(2, (16, n), 6, "U"))
+    Cm = torch.empty((2, m, n), dtype=torch.float64, device="cuda")
+    v, _ = mpx.gemm_autotune("dd", A, B, Cm, reps=1)
+    assert "_rw" not in mpx.gemm_variants("dd")[v]
+    want = mpx.gemm("dd", A, B, variant=v).cpu().numpy()
+    for i, name in enumerate(mpx.gemm_variants("dd")):
+        if "_rw" in name:
+            got = mpx.gemm("dd", A, B, variant=i).cpu().numpy()
+            assert np.array_equal(got.view(np.int64), want.view(np.int64)), name

@@ -104,8 +104,8 @@ __device__ __forceinline__ mpn<T, K> wave_sum(mpn<T, K> v) {
     return v;
 }
 
-// Sum over a 256-thread block: wave butterflies, then wave 0 adds the four
-// wave sums in wave order.  Result valid in thread 0.
+// Sum over a 256-thread block: wave butterflies, then the four wave sums
+// pairwise, (w0 + w1) + (w2 + w3).  Result valid in thread 0.
 template <typename T, int K, int AR>
 __device__ __forceinline__ mpn<T, K> block_sum(mpn<T, K> v) {
     __shared__ T sh[K][kWaves];
@@ -116,17 +116,16 @@ __device__ __forceinline__ mpn<T, K> block_sum(mpn<T, K> v) {
         for (int c = 0; c < K; ++c) sh[c][w] = v.c[c];
     }
     __syncthreads();
-    mpn<T, K> r;
+    mpn<T, K> t[kWaves];
 #pragma unroll
-    for (int c = 0; c < K; ++c) r.c[c] = sh[c][0];
+    for (int j = 0; j < kWaves; ++j)
 #pragma unroll
-    for (int j = 1; j < kWaves; ++j) {
-        mpn<T, K> t;
+        for (int c = 0; c < K; ++c) t[j].c[c] = sh[c][j];
 #pragma unroll
-        for (int c = 0; c < K; ++c) t.c[c] = sh[c][j];
-        r = ar_add<AR>(r, t);
-    }
-    return r;
+    for (int step = 1; step < kWaves; step *= 2)
+#pragma unroll
+        for (int j = 0; j + step < kWaves; j += 2 * step) t[j] = ar_add<AR>(t[j], t[j + step]);
+    return t[0];
 }
 
 // ------------------------------------------------------------------- dot --
@@ -139,24 +138,41 @@ __global__ void __launch_bounds__(kBlock)
 k_dot_partial(long long n, const T* __restrict__ x, long long psx, const T* __restrict__ y,
               long long psy, T* __restrict__ out, long long pso) {
     const long long stride = (long long)gridDim.x * kBlock;
+    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    // the first product starts the sum (no addition to zero on the chain)
     mpn<T, K> acc = mp_zero<T, K>();
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    if (i < n) acc = ar_mul<AR>(mp_load_stream<T, K>(x, psx, i), mp_load_stream<T, K>(y, psy, i));
+    for (i += stride; i < n; i += stride)
         acc = ar_add<AR>(acc, ar_mul<AR>(mp_load_stream<T, K>(x, psx, i),
                                          mp_load_stream<T, K>(y, psy, i)));
     acc = block_sum<T, K, AR>(acc);
     if (threadIdx.x == 0) mp_store<T, K>(out, pso, blockIdx.x, acc);
 }
 
-// Stage 2: one block adds the nparts partials (thread-sequential, then the
-// block tree) into K contiguous values.
+// Stage 2 for more than 64 partials: one block adds the nparts partials
+// (thread-sequential, then the block tree) into K contiguous values.
 template <typename T, int K, int AR>
 __global__ void __launch_bounds__(kBlock)
 k_sum_parts(long long nparts, const T* __restrict__ part, long long psp, T* __restrict__ out) {
     mpn<T, K> acc = mp_zero<T, K>();
-    for (long long i = threadIdx.x; i < nparts; i += kBlock)
+    if (threadIdx.x < nparts) acc = mp_load<T, K>(part, psp, threadIdx.x);
+    for (long long i = threadIdx.x + kBlock; i < nparts; i += kBlock)
         acc = ar_add<AR>(acc, mp_load<T, K>(part, psp, i));
     acc = block_sum<T, K, AR>(acc);
     if (threadIdx.x == 0) mp_store<T, K>(out, 1, 0, acc);
+}
+
+// Stage 2 for at most 64 partials: one wave, lane l holding partial l (zero
+// beyond), a butterfly over the smallest power of two `width` >= nparts
+// lanes (log2(width) dependent additions instead of the block tree's ten).
+template <typename T, int K, int AR>
+__global__ void __launch_bounds__(64)
+k_sum_parts_wave(long long nparts, int width, const T* __restrict__ part, long long psp,
+                 T* __restrict__ out) {
+    const int lane = threadIdx.x;
+    mpn<T, K> v = lane < nparts ? mp_load<T, K>(part, psp, lane) : mp_zero<T, K>();
+    for (int off = width / 2; off >= 1; off >>= 1) v = ar_add<AR>(v, mp_shfl_xor<T, K>(v, off));
+    if (lane == 0) mp_store<T, K>(out, 1, 0, v);
 }
 
 // Number of stage-1 blocks: a function of n alone (the summation tree, and so
@@ -184,7 +200,13 @@ static int launch_dot(long long n, const void* x, long long psx, const void* y, 
                                                     (T*)ws, nb);
     int st = launch_status();
     if (st != MPX_OK) return st;
-    k_sum_parts<T, K, AR><<<1, kBlock, 0, s>>>(nb, (const T*)ws, nb, (T*)result);
+    if (nb <= 64) {
+        int width = 1;
+        while (width < nb) width *= 2;
+        k_sum_parts_wave<T, K, AR><<<1, 64, 0, s>>>(nb, width, (const T*)ws, nb, (T*)result);
+    } else {
+        k_sum_parts<T, K, AR><<<1, kBlock, 0, s>>>(nb, (const T*)ws, nb, (T*)result);
+    }
     return launch_status();
 }
 

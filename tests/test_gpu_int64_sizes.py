@@ -143,10 +143,14 @@ def test_polyval_coefficients_beyond_2p31():
         assert bits_equal(estrin[:, b], want), ("estrin", b)
 
 
-@pytest.mark.parametrize("which", ["A", "At", "Bt", "C"])
+@pytest.mark.parametrize("which", ["A", "At", "B", "Bt", "C"])
 def test_gemm_leading_dimension_beyond_2p31(which):
     """m = n = 40, k = 36; the operand named by `which` is stored with leading
-    dimension 2^26 + 7, so its last row starts past element 2^31."""
+    dimension 2^26 + 7, so its last row starts past element 2^31.  The
+    default tiling and every row-wave tiling ("_rw": A through 64-bit scalar
+    addresses, B through 32-bit byte offsets from each panel's first row, or
+    the LDS tiling in their place where a transposed B's offsets would not
+    fit) give the oracle's bits."""
     m, n, k = 40, 40, 36
     ld = (1 << 26) + 7
     A = synth.mp_array(K, (m, k), 931, "U")
@@ -170,7 +174,16 @@ def test_gemm_leading_dimension_beyond_2p31(which):
         gB.copy_(to_gpu(B.transpose(0, 2, 1)))
     else:
         gB = to_gpu(B)
+    if which == "B":
+        gB = big(k, n)
+        gB.copy_(to_gpu(B))
     out = big(m, n) if which == "C" else None
     C = mpx.gemm("dd", gA, gB, transA=tA, transB=tB, out=out)
     got = to_np(C)
     assert bits_equal(got, want), first_mismatch(got, want)
+    for v, name in enumerate(mpx.gemm_variants("dd")):
+        if "_rw" in name:
+            if out is not None:
+                out.fill_(float("nan"))
+            got = to_np(mpx.gemm("dd", gA, gB, transA=tA, transB=tB, out=out, variant=v))
+            assert bits_equal(got, want), (name, first_mismatch(got, want))

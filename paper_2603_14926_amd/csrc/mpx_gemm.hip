@@ -445,20 +445,42 @@ struct Variant {
 // than 4096 tiles of 32 x 32 (16 per CU).
 static bool small_product(const GemmArgs& g) { return ceil_div(g.m, 32) * ceil_div(g.n, 32) < 4096; }
 
-// Candidate micro-tiles per precision and arithmetic (index 0 = largest
-// tile).  The conventional lists mirror the branch-free ones.
-#define MPX_TILES_DD(AR_, P_)                                                    \
-    {run_variant<double, 2, 4, 4, 8, AR_>, 64, 64, P_ "_4x4_k8"},                \
-    {run_variant<double, 2, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                \
-    {run_variant<double, 2, 2, 2, 16, AR_>, 32, 32, P_ "_2x2_k16"}
-#define MPX_TILES_TD(AR_, P_)                                                    \
-    {run_variant<double, 3, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                \
-    {run_variant<double, 3, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                \
-    {run_variant<double, 3, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"}
-#define MPX_TILES_QD(AR_, P_)                                                    \
-    {run_variant<double, 4, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                \
-    {run_variant<double, 4, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"},              \
-    {run_variant<double, 4, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"}
+// Candidate tilings per precision and arithmetic.  The conventional lists
+// (AR = 1, 2) hold exactly the branch-free ones, so the comparison of the two
+// arithmetics gives each its best tiling from the same set.
+#define MPX_TILES_DD(AR_, P_)                                                            \
+    {run_variant<double, 2, 4, 4, 8, AR_>, 64, 64, P_ "_4x4_k8"},                        \
+    {run_variant<double, 2, 2, 4, 16, AR_, true>, 32, 64, P_ "_2x4_k16_pf"},             \
+    {run_variant<double, 2, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                        \
+    {run_variant<double, 2, 2, 2, 16, AR_>, 32, 32, P_ "_2x2_k16"},                      \
+    {run_variant<double, 2, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"},                      \
+    {run_variant<double, 2, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"},                      \
+    {run_variant<double, 2, 1, 2, 16, AR_, true>, 16, 32, P_ "_1x2_k16_pf"},             \
+    {run_variant<double, 2, 1, 1, 16, AR_, true>, 16, 16, P_ "_1x1_k16_pf"},             \
+    {run_variant<double, 2, 2, 2, 16, AR_, true>, 32, 32, P_ "_2x2_k16_pf"},             \
+    {run_variant<double, 2, 2, 4, 8, AR_, true>, 32, 64, P_ "_2x4_k8_pf"},               \
+    {run_variant<double, 2, 2, 2, 32, AR_, true>, 32, 32, P_ "_2x2_k32_pf"},             \
+    {run_variant<double, 2, 1, 2, 32, AR_, true>, 16, 32, P_ "_1x2_k32_pf"},             \
+    {run_variant_rw<double, 2, 1, 4, AR_>, 4, 64, P_ "_rw1_k4", true},                   \
+    {run_variant_rw<double, 2, 2, 2, AR_>, 8, 64, P_ "_rw2_k2", true}
+#define MPX_TILES_TD(AR_, P_)                                                            \
+    {run_variant<double, 3, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                        \
+    {run_variant<double, 3, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                        \
+    {run_variant<double, 3, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"},                      \
+    {run_variant<double, 3, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"},                      \
+    {run_variant<double, 3, 1, 1, 16, AR_, true>, 16, 16, P_ "_1x1_k16_pf"},             \
+    {run_variant<double, 3, 1, 2, 16, AR_, true>, 16, 32, P_ "_1x2_k16_pf"},             \
+    {run_variant<double, 3, 2, 2, 8, AR_, true>, 32, 32, P_ "_2x2_k8_pf"},               \
+    {run_variant_rw<double, 3, 1, 4, AR_>, 4, 64, P_ "_rw1_k4", true},                   \
+    {run_variant_rw<double, 3, 2, 2, AR_>, 8, 64, P_ "_rw2_k2", true}
+#define MPX_TILES_QD(AR_, P_)                                                            \
+    {run_variant<double, 4, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                        \
+    {run_variant<double, 4, 1, 2, 16, AR_>, 16, 32, P_ "_1x2_k16"},                      \
+    {run_variant<double, 4, 1, 1, 16, AR_>, 16, 16, P_ "_1x1_k16"},                      \
+    {run_variant<double, 4, 1, 1, 16, AR_, true>, 16, 16, P_ "_1x1_k16_pf"},             \
+    {run_variant<double, 4, 1, 2, 16, AR_, true>, 16, 32, P_ "_1x2_k16_pf"},             \
+    {run_variant<double, 4, 2, 2, 8, AR_, true>, 32, 32, P_ "_2x2_k8_pf"},               \
+    {run_variant_rw<double, 4, 1, 2, AR_>, 4, 64, P_ "_rw1_k2", true}
 
 static const std::vector<Variant>& variants(int prec) {
     // DD also offers 16 x 32 and 16 x 16 tiles: at n = 512 the 32 x 32 tile
@@ -469,32 +491,9 @@ static const std::vector<Variant>& variants(int prec) {
     // workgroup of 4R x 64) come last, so the untuned heuristic keeps the LDS
     // tilings; the autotuner tries them for small products (small_product)
     // and picks them where they win (n = 512 and 1024).
-    static const std::vector<Variant> dd = {{run_variant<double, 2, 4, 4, 8, AR_BF>, 64, 64, "dd_4x4_k8"},
-                                            {run_variant<double, 2, 2, 4, 16, AR_BF, true>, 32, 64, "dd_2x4_k16_pf"},
-                                            {run_variant<double, 2, 2, 4, 8, AR_BF>, 32, 64, "dd_2x4_k8"},
-                                            {run_variant<double, 2, 2, 2, 16, AR_BF>, 32, 32, "dd_2x2_k16"},
-                                            {run_variant<double, 2, 1, 2, 16, AR_BF>, 16, 32, "dd_1x2_k16"},
-                                            {run_variant<double, 2, 1, 1, 16, AR_BF>, 16, 16, "dd_1x1_k16"},
-                                            {run_variant<double, 2, 1, 2, 16, AR_BF, true>, 16, 32, "dd_1x2_k16_pf"},
-                                            {run_variant<double, 2, 1, 1, 16, AR_BF, true>, 16, 16, "dd_1x1_k16_pf"},
-                                            {run_variant<double, 2, 2, 2, 16, AR_BF, true>, 32, 32, "dd_2x2_k16_pf"},
-                                            {run_variant<double, 2, 2, 4, 8, AR_BF, true>, 32, 64, "dd_2x4_k8_pf"},
-                                            {run_variant<double, 2, 2, 2, 32, AR_BF, true>, 32, 32, "dd_2x2_k32_pf"},
-                                            {run_variant<double, 2, 1, 2, 32, AR_BF, true>, 16, 32, "dd_1x2_k32_pf"},
-                                            {run_variant_rw<double, 2, 1, 4, AR_BF>, 4, 64, "dd_rw1_k4", true},
-                                            {run_variant_rw<double, 2, 2, 2, AR_BF>, 8, 64, "dd_rw2_k2", true}};
-    static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td"),
-                                            {run_variant<double, 3, 1, 1, 16, AR_BF>, 16, 16, "td_1x1_k16"},
-                                            {run_variant<double, 3, 1, 1, 16, AR_BF, true>, 16, 16, "td_1x1_k16_pf"},
-                                            {run_variant<double, 3, 1, 2, 16, AR_BF, true>, 16, 32, "td_1x2_k16_pf"},
-                                            {run_variant<double, 3, 2, 2, 8, AR_BF, true>, 32, 32, "td_2x2_k8_pf"},
-                                            {run_variant_rw<double, 3, 1, 4, AR_BF>, 4, 64, "td_rw1_k4", true},
-                                            {run_variant_rw<double, 3, 2, 2, AR_BF>, 8, 64, "td_rw2_k2", true}};
-    static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd"),
-                                            {run_variant<double, 4, 1, 1, 16, AR_BF, true>, 16, 16, "qd_1x1_k16_pf"},
-                                            {run_variant<double, 4, 1, 2, 16, AR_BF, true>, 16, 32, "qd_1x2_k16_pf"},
-                                            {run_variant<double, 4, 2, 2, 8, AR_BF, true>, 32, 32, "qd_2x2_k8_pf"},
-                                            {run_variant_rw<double, 4, 1, 2, AR_BF>, 4, 64, "qd_rw1_k2", true}};
+    static const std::vector<Variant> dd = {MPX_TILES_DD(AR_BF, "dd")};
+    static const std::vector<Variant> td = {MPX_TILES_TD(AR_BF, "td")};
+    static const std::vector<Variant> qd = {MPX_TILES_QD(AR_BF, "qd")};
     static const std::vector<Variant> ff = {
         {run_variant<float, 2, 4, 8, 8, AR_BF>, 64, 128, "ff_4x8_k8"},
         {run_variant<float, 2, 4, 4, 8, AR_BF>, 64, 64, "ff_4x4_k8"},

@@ -66,7 +66,8 @@ def test_dot_within_bound(p, K, mode, n):
 
 
 @pytest.mark.parametrize("p,K,mode", MODES)
-@pytest.mark.parametrize("mnk", [(1, 1, 1), (33, 17, 65), (100, 70, 129), (64, 64, 0)])
+@pytest.mark.parametrize("mnk", [(1, 1, 1), (33, 17, 65), (100, 70, 129), (64, 64, 0),
+                                 (5, 130, 12), (67, 3, 7)])
 def test_gemm_bit_exact_all_variants(p, K, mode, mnk):
     m, n, k = mnk
     A = _mixed(K, (m, k), 50 + m)
@@ -75,7 +76,9 @@ def test_gemm_bit_exact_all_variants(p, K, mode, mnk):
         want = oracle.gemm(K, A, B)
     gA, gB = to_gpu(A), to_gpu(B)
     names = mpx.gemm_variants(p)
-    assert len(names) == 3 and all(nm.startswith(p + "_") for nm in names)
+    # the conventional arithmetic has exactly the branch-free tilings
+    base = p.split("_")[0]
+    assert names == [p + nm[len(base):] for nm in mpx.gemm_variants(base)]
     for v in range(len(names)):
         got = to_np(mpx.gemm(p, gA, gB, variant=v))
         assert bits_equal(got, want), (v, first_mismatch(got, want))

@@ -445,7 +445,11 @@ struct Variant {
 // than 4096 tiles of 32 x 32 (16 per CU).
 static bool small_product(const GemmArgs& g) { return ceil_div(g.m, 32) * ceil_div(g.n, 32) < 4096; }
 
-// Candidate tilings per precision and arithmetic.  The conventional lists
+// Candidate tilings per precision and arithmetic (row-wave panel depths: the
+// deepest whose double-buffered A panels fit the scalar registers without
+// spill code inside the loop, or a shallower one where that measured faster;
+// DD with two rows and 4-deep panels keeps a few spills in its prologue).
+// The conventional lists
 // (AR = 1, 2) hold exactly the branch-free ones, so the comparison of the two
 // arithmetics gives each its best tiling from the same set.
 #define MPX_TILES_DD(AR_, P_)                                                            \
@@ -462,7 +466,8 @@ static bool small_product(const GemmArgs& g) { return ceil_div(g.m, 32) * ceil_d
     {run_variant<double, 2, 2, 2, 32, AR_, true>, 32, 32, P_ "_2x2_k32_pf"},             \
     {run_variant<double, 2, 1, 2, 32, AR_, true>, 16, 32, P_ "_1x2_k32_pf"},             \
     {run_variant_rw<double, 2, 1, 4, AR_>, 4, 64, P_ "_rw1_k4", true},                   \
-    {run_variant_rw<double, 2, 2, 2, AR_>, 8, 64, P_ "_rw2_k2", true}
+    {run_variant_rw<double, 2, 2, 2, AR_>, 8, 64, P_ "_rw2_k2", true},                  \
+    {run_variant_rw<double, 2, 2, 4, AR_>, 8, 64, P_ "_rw2_k4", true}
 #define MPX_TILES_TD(AR_, P_)                                                            \
     {run_variant<double, 3, 2, 4, 8, AR_>, 32, 64, P_ "_2x4_k8"},                        \
     {run_variant<double, 3, 2, 2, 8, AR_>, 32, 32, P_ "_2x2_k8"},                        \

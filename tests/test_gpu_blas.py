@@ -174,16 +174,45 @@ def test_gemm_transposes_bit_exact(p, K, dt):
 
 @pytest.mark.parametrize("p,K,dt", PREC_K)
 def test_gemm_512_full_bit_exact(p, K, dt):
+    """n = 512 on the default tiling and on every row-wave tiling (the
+    autotuner's choices at this size): 74 sampled entries spread over all
+    rows and column groups."""
     n = 512
     A = synth.mp_array(K, (n, n), 80, "U", dtype=dt)
     B = synth.mp_array(K, (n, n), 81, "U", dtype=dt)
     rows = np.arange(0, n, 7); cols = (rows * 13 + 5) % n
-    got = to_np(mpx.gemm(p, to_gpu(A), to_gpu(B)))
     if p == "ff":
         want = oracle.ff_gemm_entries(A, B, rows, cols)
     else:
         want = oracle.gemm_entries(K, A, B, rows, cols)
+    gA, gB = to_gpu(A), to_gpu(B)
+    got = to_np(mpx.gemm(p, gA, gB))
     assert bits_equal(np.ascontiguousarray(got[:, rows, cols]), want)
+    for v, name in enumerate(mpx.gemm_variants(p)):
+        if "_rw" in name:
+            got = to_np(mpx.gemm(p, gA, gB, variant=v))
+            assert bits_equal(np.ascontiguousarray(got[:, rows, cols]), want), name
+
+
+@pytest.mark.parametrize("p,K,dt", PREC_K)
+def test_gemm_1024_row_wave_sampled_bit_exact(p, K, dt):
+    """n = 1024, wide-exponent inputs, every row-wave tiling: 40 sampled
+    entries (corners, the edges of column groups, interior)."""
+    n = 1024
+    A = synth.mp_array(K, (n, n), 84, "W", dtype=dt)
+    B = synth.mp_array(K, (n, n), 85, "W", dtype=dt)
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, 0, n - 1, n - 1, 511, 3], rng.integers(0, n, 34)])
+    cols = np.concatenate([[0, n - 1, 0, n - 1, 63, 64], rng.integers(0, n, 34)])
+    if p == "ff":
+        want = oracle.ff_gemm_entries(A, B, rows, cols)
+    else:
+        want = oracle.gemm_entries(K, A, B, rows, cols)
+    gA, gB = to_gpu(A), to_gpu(B)
+    for v, name in enumerate(mpx.gemm_variants(p)):
+        if "_rw" in name:
+            got = to_np(mpx.gemm(p, gA, gB, variant=v))
+            assert bits_equal(np.ascontiguousarray(got[:, rows, cols]), want), name
 
 
 @pytest.mark.parametrize("p,K,dt,dist", [("qd", 4, np.float64, "U"), ("qd", 4, np.float64, "W"),

@@ -243,7 +243,11 @@ int mpx_gemm_batched_autotune(mpx_gemm_plan plan, const void *A, int64_t psA, co
 int mpx_gemm_plan_destroy(mpx_gemm_plan plan);
 
 /* ---------------------------------------------------------- GEMM tuning --
- * The GEMM has several register/LDS tilings ("variants"); all produce the
+ * The GEMM has several tilings ("variants"): LDS-staged register tiles
+ * ("<p>_<TM>x<TN>_k<BK>", "_pf" reading the next step's operands early) and
+ * row-wave tilings ("<p>_rw<R>_k<BK>": each wave owns R rows x 64 columns,
+ * A through scalar loads, no LDS); the conventional arithmetic has the same
+ * tilings under its own prefix (e.g. "dd_nobf_rw2_k4"); all produce the
  * same bits.  mpx_gemm picks one per (precision, transposes, log2 size
  * bucket): a tiling named in the environment variable MPX_GEMM_VARIANT
  * (comma-separated names; the first that belongs to the precision), else

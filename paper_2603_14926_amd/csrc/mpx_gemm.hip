@@ -784,6 +784,44 @@ __device__ __forceinline__ void wave_tile(const GbItem& w, const GbProb& q, cons
     }
 }
 
+// A flat edge item of the mixed tiling: 64 consecutive entries, in row-major
+// order, of one of a product's two edge strips left by its BM x BN interior
+// tiles (n0 = -1: the bottom strip, rows [fm, m) x columns [0, n); n0 = -2:
+// the right strip, rows [0, fm) x columns [fn, n)), starting at entry m0 of
+// the strip.  Each lane computes its entry like wave_tile; only the strip's
+// last item has idle lanes.
+template <typename T, int K, int U, int AR, int BM, int BN>
+__device__ __forceinline__ void wave_flat(const GbItem& w, const GbProb& q, const T* __restrict__ A,
+                                          long long psA, const T* __restrict__ B, long long psB,
+                                          T* __restrict__ C, long long psC) {
+    const int fm = q.m / BM * BM, fn = q.n / BN * BN;
+    const int r0 = w.n0 == -1 ? fm : 0, c0 = w.n0 == -1 ? 0 : fn;
+    const int wid = w.n0 == -1 ? q.n : q.n - fn;
+    const int cnt = w.n0 == -1 ? (q.m - fm) * q.n : fm * (q.n - fn);
+    const int t = w.m0 + (int)(threadIdx.x & 63);
+    const int tt = t < cnt ? t : cnt - 1;  // idle lanes repeat the last entry, unstored
+    const int row = r0 + tt / wid, col = c0 + tt % wid;
+    const long long ar = (long long)row * q.k;
+    const T* __restrict__ Ap = A + q.a;
+    const T* __restrict__ Bp = B + q.b;
+    mpn<T, K> acc = mp_zero<T, K>();
+    int l = 0;
+    for (; l + U <= q.k; l += U) {
+        mpn<T, K> a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = mp_load<T, K>(Ap, psA, ar + l + u);
+            b[u] = mp_load<T, K>(Bp, psB, (long long)(l + u) * q.n + col);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = ar_add<AR>(acc, ar_mul<AR>(a[u], b[u]));
+    }
+    for (; l < q.k; ++l)
+        acc = ar_add<AR>(acc, ar_mul<AR>(mp_load<T, K>(Ap, psA, ar + l),
+                                          mp_load<T, K>(Bp, psB, (long long)l * q.n + col)));
+    if (t < cnt) mp_store<T, K>(C + q.c, psC, (long long)row * q.n + col, acc);
+}
+
 template <typename T, int K, int U, int AR>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
@@ -802,7 +840,8 @@ k_gemm_batched_wave(int nitems, const GbItem* __restrict__ items,
 }
 
 // Mixed tiling: the interior of each product in 16 TM x 16 TN workgroup
-// tiles and its ragged edges in 8 x 8 wave tiles.  A work unit is four
+// tiles and its ragged edges in 8 x 8 wave tiles, or (flat edges) in waves of
+// 64 consecutive entries of each edge strip.  A work unit is four
 // consecutive items: a workgroup tile (item 1 has p = kGbTileUnit, items 2
 // and 3 unused) or up to four wave tiles, one per wave (p = -1: none).  The
 // unit kind is read by the whole workgroup, so the barriers inside the
@@ -834,7 +873,12 @@ k_gemm_batched_mixed(int nunits, const GbItem* __restrict__ items,
                                                               w.m0, w.n0, sA, sB);
         } else {
             const GbItem w = unit[wv];
-            if (w.p >= 0) wave_tile<T, K, U, AR>(w, probs[w.p], A, psA, B, psB, C, psC);
+            if (w.p >= 0) {
+                if (w.n0 < 0)
+                    wave_flat<T, K, U, AR, 16 * TM, 16 * TN>(w, probs[w.p], A, psA, B, psB, C, psC);
+                else
+                    wave_tile<T, K, U, AR>(w, probs[w.p], A, psA, B, psB, C, psC);
+            }
         }
     }
 }
@@ -845,6 +889,7 @@ struct GbVariant {
     int bm, bn;
     int per_wg;  // items a workgroup runs at once (4 for wave tiles)
     bool mixed;  // work units of the mixed tiling (bm x bn interior, 8 x 8 edges)
+    bool flat = false;  // mixed, with the edges as flat 64-entry waves
 };
 
 template <typename T, int K, int TM, int TN, int BK, int AR, bool PF = false>
@@ -886,17 +931,25 @@ static std::vector<GbVariant> gb_variants(int prec) {
 #define MPX_GBP(T_, K_, TM_, TN_, BK_, AR_) GbVariant{gb_launch<T_, K_, TM_, TN_, BK_, AR_, true>, 16 * TM_, 16 * TN_, 1, false}
 #define MPX_GBMP(T_, K_, TM_, TN_, BK_, U_, AR_) \
     GbVariant{gb_launch_mixed<T_, K_, TM_, TN_, BK_, U_, AR_, true>, 16 * TM_, 16 * TN_, 1, true}
+    // mixed with flat edges (the same kernels; only the work list differs)
+#define MPX_GBMF(T_, K_, TM_, TN_, BK_, U_, AR_) \
+    GbVariant{gb_launch_mixed<T_, K_, TM_, TN_, BK_, U_, AR_, true>, 16 * TM_, 16 * TN_, 1, true, true}
     switch (prec) {
         case MPX_DD: return {MPX_GBW(double, 2, 4, AR_BF), MPX_GB(double, 2, 2, 2, 16, AR_BF), MPX_GB(double, 2, 2, 4, 8, AR_BF), MPX_GB(double, 2, 4, 4, 8, AR_BF),
-                             MPX_GBP(double, 2, 2, 2, 16, AR_BF), MPX_GBMP(double, 2, 1, 1, 16, 4, AR_BF)};
+                             MPX_GBP(double, 2, 2, 2, 16, AR_BF), MPX_GBMP(double, 2, 1, 1, 16, 4, AR_BF),
+                             MPX_GBMF(double, 2, 1, 1, 16, 4, AR_BF)};
         case MPX_TD: return {MPX_GBM(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBW(double, 3, 2, AR_BF), MPX_GB(double, 3, 1, 2, 16, AR_BF), MPX_GB(double, 3, 2, 2, 8, AR_BF), MPX_GB(double, 3, 2, 4, 8, AR_BF),
-                             MPX_GBMP(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBMP(double, 3, 1, 1, 16, 2, AR_BF)};
+                             MPX_GBMP(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBMP(double, 3, 1, 1, 16, 2, AR_BF),
+                             MPX_GBMF(double, 3, 1, 2, 16, 2, AR_BF), MPX_GBMF(double, 3, 1, 1, 16, 2, AR_BF)};
         case MPX_QD: return {MPX_GBM(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBW(double, 4, 2, AR_BF), MPX_GB(double, 4, 1, 1, 16, AR_BF), MPX_GB(double, 4, 1, 2, 16, AR_BF), MPX_GB(double, 4, 2, 2, 8, AR_BF),
-                             MPX_GBMP(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBMP(double, 4, 1, 2, 16, 2, AR_BF)};
+                             MPX_GBMP(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBMP(double, 4, 1, 2, 16, 2, AR_BF),
+                             MPX_GBMF(double, 4, 1, 1, 16, 2, AR_BF), MPX_GBMF(double, 4, 1, 2, 16, 2, AR_BF)};
         case MPX_FF: return {MPX_GBW(float, 2, 4, AR_BF), MPX_GB(float, 2, 2, 2, 16, AR_BF), MPX_GB(float, 2, 2, 4, 8, AR_BF), MPX_GB(float, 2, 4, 4, 8, AR_BF),
-                             MPX_GBP(float, 2, 2, 2, 16, AR_BF), MPX_GBMP(float, 2, 1, 1, 16, 4, AR_BF)};
+                             MPX_GBP(float, 2, 2, 2, 16, AR_BF), MPX_GBMP(float, 2, 1, 1, 16, 4, AR_BF),
+                             MPX_GBMF(float, 2, 1, 1, 16, 4, AR_BF)};
         default: return {};
     }
+#undef MPX_GBMF
 #undef MPX_GBMP
 #undef MPX_GBP
 #undef MPX_GBM
@@ -969,10 +1022,17 @@ static int gemm_batched_plan(mpx_gemm_plan* out, int prec, int64_t count, const 
                 const int fm = m / v.bm * v.bm, fn = n / v.bn * v.bn;
                 for (int r = 0; r < fm; r += v.bm)
                     for (int c = 0; c < fn; c += v.bn) tiles.push_back(GbItem{(int)i, r, c});
-                for (int r = fm; r < m; r += 8)
-                    for (int c = 0; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
-                for (int r = 0; r < fm; r += 8)
-                    for (int c = fn; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
+                if (v.flat) {
+                    // 64-entry runs of the bottom strip (n0 = -1) and the right strip (n0 = -2)
+                    const long long bottom = (long long)(m - fm) * n, right = (long long)fm * (n - fn);
+                    for (long long t = 0; t < bottom; t += 64) edges.push_back(GbItem{(int)i, (int)t, -1});
+                    for (long long t = 0; t < right; t += 64) edges.push_back(GbItem{(int)i, (int)t, -2});
+                } else {
+                    for (int r = fm; r < m; r += 8)
+                        for (int c = 0; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
+                    for (int r = 0; r < fm; r += 8)
+                        for (int c = fn; c < n; c += 8) edges.push_back(GbItem{(int)i, r, c});
+                }
             }
             std::stable_sort(tiles.begin(), tiles.end(), by_k);
             std::stable_sort(edges.begin(), edges.end(), by_k);

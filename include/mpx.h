@@ -213,7 +213,8 @@ int mpx_gemm_strassen(int prec, int64_t m, int64_t n, int64_t k, const void *A, 
  * naive triple loop's sequence).  The tilings offered: mpx_gemm's (some
  * with the LDS-prefetching panel loop), 8 x 8 tiles computed by one wave
  * each, and mixed tilings with workgroup tiles over each product's interior
- * and wave tiles over its ragged edges.  Operands are packed per component
+ * and, over its ragged edges, 8 x 8 wave tiles or waves of 64 consecutive
+ * entries of each edge strip.  Operands are packed per component
  * plane:
  * A_p starts at element sum_{q<p} m_q k_q, row-major with ld = k_p; B_p at
  * sum_{q<p} k_q n_q (ld = n_p); C_p at sum_{q<p} m_q n_q (ld = n_p); plane

@@ -227,6 +227,18 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
                                                 n0, sA, sB);
 }
 
+// Raw buffer loads: word 3 of a gfx9 buffer resource with a 32-bit data
+// format and no swizzle; the range is left unlimited (the launcher bounds
+// every offset).
+constexpr int kBufWord3 = 0x00020000;
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+
 // Row-wave tiling, for products too small to give every SIMD several waves of
 // the LDS-tiled kernel: each wave64 owns R rows x 64 columns of C, one column
 // per lane, so at every step all lanes of a wave multiply by the same A
@@ -242,19 +254,8 @@ k_gemm(int m, int n, int k, const T* __restrict__ A, long long lda, long long ps
 // order and are waited for all at once, comes before them) and overlap the
 // remaining steps.  Each C_ij is still accumulated in ascending l from zero
 // with the same operation, so the bits equal those of every other tiling.
-// The launcher checks that the per-lane byte offsets fit in 32 bits.
-// Raw buffer loads: word 3 of a gfx9 buffer resource with a 32-bit data
-// format and no swizzle; the range is left unlimited (the launcher bounds
-// every offset).
-constexpr int kBufWord3 = 0x00020000;
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
-    if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
-}
-
+// The launcher checks that B's byte offsets from a panel's first row (or
+// column) fit in 31 bits, and runs an LDS tiling where they would not.
 template <typename T, int K, int R, int BK, bool TA, bool TB, int AR>
 __global__ void __launch_bounds__(kGemmThreads)
 k_gemm_rw(int m, int n, int k, const T* __restrict__ A, long long lda, long long psA,

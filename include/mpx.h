@@ -279,6 +279,7 @@ int mpx_gemm_variant(int prec, int variant, int transA, int transB, int64_t m, i
  * rounds over all variants (a variant's time is its faster round), skipping
  * the row-wave tilings ("_rw" names) for products with 4096 or more tiles of
  * 32 x 32, where they re-read B far more and run no faster; remember the fastest
+ * (the size heuristic's tiling unless another is at least 1 % faster)
  * for this bucket and return its index (>= 0) or a negative status; *best_ms
  * (nullable) receives its mean time per call.  Synchronises `stream`; must not be called under graph
  * capture. */

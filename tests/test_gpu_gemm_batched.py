@@ -58,17 +58,22 @@ def test_batched_bit_exact_every_tiling(p, K, dt):
 
 
 def test_batched_matches_single_gemm_at_larger_sizes():
+    """Products of 60..300 (edge strips of hundreds of entries: several flat
+    64-entry waves per strip) on every tiling equal mpx_gemm's bits."""
     K = 4
     ms, ns, ks, As, Bs = _batch(K, np.float64, 12, 7, lo=60, hi=300)
     plan = mpx.GemmBatchPlan("qd", ms, ns, ks)
     A = to_gpu(_pack(K, np.float64, As)); B = to_gpu(_pack(K, np.float64, Bs))
     _, _, c_off, (_, _, tc) = plan.offsets()
-    got = to_np(plan.run(A, B, torch.empty((K, tc), dtype=torch.float64, device="cuda")))
-    for i, (Ai, Bi) in enumerate(zip(As, Bs)):
-        m, n = Ai.shape[1], Bi.shape[2]
-        single = to_np(mpx.gemm("qd", to_gpu(Ai), to_gpu(Bi)))
-        g = np.ascontiguousarray(got[:, c_off[i]:c_off[i] + m * n].reshape(K, m, n))
-        assert bits_equal(g, single), i
+    singles = [to_np(mpx.gemm("qd", to_gpu(Ai), to_gpu(Bi))) for Ai, Bi in zip(As, Bs)]
+    for v in range(plan.variant_count()):
+        plan.set_variant(v)
+        Cm = torch.full((K, tc), float("nan"), dtype=torch.float64, device="cuda")
+        got = to_np(plan.run(A, B, Cm))
+        for i, (Ai, Bi) in enumerate(zip(As, Bs)):
+            m, n = Ai.shape[1], Bi.shape[2]
+            g = np.ascontiguousarray(got[:, c_off[i]:c_off[i] + m * n].reshape(K, m, n))
+            assert bits_equal(g, singles[i]), (v, i)
 
 
 def test_batched_graph_replay():

@@ -140,9 +140,10 @@ def _oracle_gemm(p, K, A, B, tA, tB):
 @pytest.mark.parametrize("p,K,dt", PREC_K)
 # (5, 130, 12) and (67, 3, 7): odd and single panel counts of the row-wave
 # tilings' 2-, 4- and 8-deep panels, ragged rows within a wave and a ragged
-# third column group; (9, 64, 8): k exactly one 8-deep panel, n one full group
+# third column group; (9, 64, 8): k exactly one 8-deep panel, n one full group;
+# (3, 70, 3001): a long k (hundreds of panels and an odd tail)
 @pytest.mark.parametrize("mnk", [(1, 1, 1), (33, 17, 65), (100, 70, 129), (64, 64, 0),
-                                 (5, 130, 12), (67, 3, 7), (9, 64, 8)])
+                                 (5, 130, 12), (67, 3, 7), (9, 64, 8), (3, 70, 3001)])
 def test_gemm_bit_exact_all_variants(p, K, dt, mnk):
     m, n, k = mnk
     A = synth.mp_array(K, (m, k), 50 + m, "W", dtype=dt)
